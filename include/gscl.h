@@ -1,0 +1,324 @@
+/*
+ * gscl.h -- C-ABI of the MI355X (gfx950) stencil library.
+ *
+ * The library implements the data-parallel hot path of GSCL (Bianco & Varetto,
+ * "A Generic Library for Stencil Computations"): the do_all iteration space,
+ * which applies a stencil operator at every point of a regular 2D/3D grid
+ * reading several input grids at fixed offsets and writing the core element of
+ * several output grids (Section 3), and the do_reduce iteration space, which
+ * combines per-point values with a commutative operator (Section 3).  Around
+ * them sit the context phases of Section 4 (Fig. 2b), an iterative solver that
+ * fuses the convergence test into the sweep (Section 5.2), mixed-precision
+ * iterative refinement, and a batched multi-grid executor for serving many
+ * solves at once.
+ *
+ * Conventions for every entry point:
+ *   - Return value: GSCL_OK (0) or a negative GSCL_ERR_* code; gscl_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - Arguments are validated on the host before any HIP call; a rejected call
+ *     has no side effect.
+ *   - Device memory is caller-owned.  A grid handle borrows the memory passed to
+ *     gscl_grid_create; the caller keeps it alive until gscl_grid_destroy.  The
+ *     library owns only its context scratch (reduction partials, tickets,
+ *     graphs, batch slot tables).
+ *   - Calls are asynchronous on the context's HIP stream, except those that
+ *     return a host scalar (do_reduce / fused reductions without a device
+ *     result pointer, solve, batch_poll, end), which synchronize the stream.
+ *   - One context per host thread.  Contexts on one device may share grids.
+ *   - The library never allocates in gscl_do_all / gscl_do_reduce /
+ *     gscl_batch_step: scratch is reserved by gscl_begin and grows only in
+ *     gscl_reserve, so these calls may be captured into a HIP graph.
+ */
+#ifndef GSCL_H
+#define GSCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+    GSCL_OK = 0,
+    GSCL_ERR_ARG = -1,          /* null pointer, bad enum, bad count, misaligned memory */
+    GSCL_ERR_STATE = -2,        /* iteration space called outside begin/end (Section 4) */
+    GSCL_ERR_SHAPE = -3,        /* extents differ between grids of one call, bad ndim */
+    GSCL_ERR_HALO = -4,         /* a grid is read beyond its declared halo */
+    GSCL_ERR_ALIAS = -5,        /* an output aliases a grid read at a non-zero offset */
+    GSCL_ERR_DTYPE = -6,        /* element type not accepted by the operator */
+    GSCL_ERR_NOMEM = -7,        /* scratch, workspace or batch budget exhausted */
+    GSCL_ERR_NOCONV = -8,       /* solver hit max_sweeps before rtol */
+    GSCL_ERR_HIP = -9,          /* a HIP runtime call failed (message has the HIP error) */
+    GSCL_ERR_NUMERIC = -10,     /* NaN/Inf met by a solver */
+    GSCL_ERR_UNSUPPORTED = -11  /* valid request this build has no kernel for */
+};
+
+/* ---- element types, boundary rules -------------------------------------- */
+typedef enum {
+    GSCL_F64 = 0, GSCL_F32 = 1, GSCL_F16 = 2, GSCL_BF16 = 3,
+    GSCL_U8 = 4, GSCL_I16 = 5, GSCL_U32 = 6
+} gscl_dtype;
+
+/* What a read outside the interior returns (the halo the stencil shape lets
+ * an operator touch, Section 3).  Halo values are synthesized by the kernels;
+ * no halo is stored, so no halo-fill pass ever runs.
+ *   DIRICHLET: the constant bc_value;  PERIODIC: the interior point at the
+ *   index modulo the extent;  CLAMP: the nearest interior point.            */
+typedef enum { GSCL_BC_DIRICHLET = 0, GSCL_BC_PERIODIC = 1, GSCL_BC_CLAMP = 2 } gscl_bc;
+
+/* A regular grid G(i0, i1[, i2]) (Section 3).
+ *   ndim      2 or 3.
+ *   n[0..2]   interior extents along x, y, z.  x (i0) is unit-stride.  For
+ *             ndim = 2, n[2] >= 1 counts independent 2D layers stored one
+ *             after another; no operator reads across layers.
+ *   halo      the widest offset an operator may read around the core element
+ *             (the stencil shape); 0..4.
+ *   dtype     gscl_dtype.   bc / bc_value: boundary rule (see gscl_bc).
+ *   pitch[0]  elements between rows (y stride), pitch[1] elements between
+ *             planes (z stride); 0 selects the library default (rows padded to
+ *             a multiple of 16 elements, planes packed).  Rows must start 16-byte aligned:
+ *             pitch[0] * element size must be a multiple of 16.
+ * Element (i, j, k) lives at base + k*pitch[1] + j*pitch[0] + i.            */
+typedef struct {
+    int32_t ndim;
+    int32_t halo;
+    int64_t n[3];
+    int32_t dtype;
+    int32_t bc;
+    double bc_value;
+    int64_t pitch[2];
+} gscl_grid_desc;
+
+typedef struct gscl_ctx gscl_ctx;
+typedef struct gscl_grid gscl_grid;
+typedef struct gscl_graph gscl_graph;
+typedef struct gscl_batch gscl_batch;
+
+/* ---- stencil operators -------------------------------------------------- */
+/* Operator kinds.  Each kind fixes which input grids are read at offsets
+ * ("neighbour-read") and which only at the core element ("pointwise"), the
+ * access traits that Section 3 says matter most for performance.
+ *
+ * GSCL_K_LINEAR (Section 3, Fig. 1b): any linear operator given as terms.
+ *   out[t.out](p) += t.w * (t.coef >= 0 ? in[t.coef](p) : 1) * in[t.grid](p + d_t)
+ *   F64 or F32 grids (all of one type), ndim 2 or 3, any offsets within halo.
+ * GSCL_K_WJACOBI (Section 5.2 averaging, weighted, with source):
+ *   in = {u} or {u, f}; out = {u'}; p[0] = omega, p[1] = h^2.
+ *   S = sum of the 2*ndim neighbours; u' = (1-omega) u + omega (S - h^2 f)/(2 ndim).
+ *   F64 or F32.  Fused reduce operands: UPDATE = u' - u,
+ *   RESIDUAL = f - (S - 2 ndim u)/h^2 (residual of the input u).
+ * GSCL_K_VARCOEF7 (Section 2, multi-grid): in = {u, c0..c6, s}, out = {u', r, |F|}.
+ *   out = sum_k c_k u(p+e_k), e_0 = 0, e_1..e_6 = +x,-x,+y,-y,+z,-z; C = sum c_k;
+ *   u' = (out + s)/C; r = s + out - C u;
+ *   F_d = (c_{+d}(u(p+e_d)-u) + c_{-d}(u-u(p-e_d)))/2; |F| = |(F_x,F_y,F_z)|.
+ *   F32 (F64 accepted).  Fused operand RESIDUAL = r.
+ * GSCL_K_IMG_BOX5_LAP (Section 1, image filters): in = {img U8, ndim 2,
+ *   layers allowed, CLAMP}; out = {box U8, lap I16}; p[0] = 4 or 8.
+ *   box = floor((S + 12)/25), S the 5x5 window sum; lap = N+S+E+W-4C (p[0]=4)
+ *   or sum of 8 neighbours - 8C (p[0]=8).  Exact integer arithmetic.
+ * GSCL_K_VC13_APPLY (fourth-order 13-point, several fields sharing 10
+ *   coefficient grids): in = {u_0..u_{F-1}, c0..c9}, out = {v_0..v_{F-1}};
+ *   v_f = A u_f with
+ *   A u = c0 u - kappa sum_d [ (4/3)(c_{d+}(u(p+e_d)-u) + c_{d-}(u(p-e_d)-u))
+ *                              - (1/12) c_{d2} (u(p+2e_d) + u(p-2e_d) - 2u) ],
+ *   c1..c6 = c_{x+}, c_{x-}, c_{y+}, c_{y-}, c_{z+}, c_{z-}, c7..c9 = c_{x2,y2,z2}.
+ *   p[0] = kappa, p[2] = F (number of fields, 1 or 5).  Storage F32/F16/BF16
+ *   (math F32) or F64.  Halo 2.
+ * GSCL_K_VC13_JACOBI: in = {d_0..d_{F-1}, g_0..g_{F-1}, c0..c9},
+ *   out = {d'_f}: d' = d + omega (g - A d) / D, D the diagonal of A.
+ *   p[0] = kappa, p[1] = omega, p[2] = F.  Storage as VC13_APPLY.
+ * GSCL_K_VC13_RESID: in = {x_0..x_{F-1} (F64), b_0..b_{F-1} (F64), c0..c9
+ *   (any float storage)}, out = {r_f} (F32): r = b - A x in F64, stored F32.
+ *   Fused operands: RESIDUAL (r in F64).                                    */
+enum {
+    GSCL_K_LINEAR = 0,
+    GSCL_K_WJACOBI = 1,
+    GSCL_K_VARCOEF7 = 2,
+    GSCL_K_IMG_BOX5_LAP = 3,
+    GSCL_K_VC13_APPLY = 4,
+    GSCL_K_VC13_JACOBI = 5,
+    GSCL_K_VC13_RESID = 6
+};
+
+typedef struct {
+    int32_t out;                /* output index the term accumulates into */
+    int32_t grid;               /* input grid read at offset (dx, dy, dz) */
+    int32_t dx, dy, dz;
+    int32_t coef;               /* input grid read at the core element, -1 = none */
+    double w;
+} gscl_term;
+
+#define GSCL_MAX_TERMS 64
+
+typedef struct {
+    int32_t kind;
+    int32_t nterms;             /* LINEAR only */
+    const gscl_term *terms;     /* LINEAR only, host memory, copied by the call */
+    double p[8];                /* kind parameters (see above) */
+} gscl_stencil_desc;
+
+/* ---- reductions (do_reduce, Section 3) ---------------------------------- */
+enum {
+    GSCL_R_SUM = 0,             /* sum of the values */
+    GSCL_R_SUMSQ = 1,           /* sum of squares */
+    GSCL_R_L2 = 2,              /* sqrt of the sum of squares */
+    GSCL_R_MAXABS = 3,          /* max |value|; NaN anywhere gives NaN */
+    GSCL_R_ALL_LE = 4           /* 1.0 if every |value| <= eps else 0.0 (NaN -> 0.0) */
+};
+enum {
+    GSCL_RV_OUT0 = 0,           /* fused: the first output value */
+    GSCL_RV_UPDATE = 1,         /* fused: first output minus first input at the core */
+    GSCL_RV_RESIDUAL = 2        /* fused: the kind's residual (see kinds) */
+};
+typedef struct {
+    int32_t op;                 /* GSCL_R_* */
+    int32_t operand;            /* GSCL_RV_* (fused reductions only) */
+    double eps;                 /* ALL_LE threshold */
+    void *dev_result;           /* optional device double*: result written there,
+                                   asynchronously; the host result may then be NULL */
+} gscl_reduce_desc;
+
+/* ---- context (Section 4, Fig. 2b) ---------------------------------------- */
+/* gscl_init: bind a new context to HIP device `device` (GSCL_Init).  Performs
+ * no HIP call.  States: INIT -> ACTIVE (begin) <-> ENDED (end) -> FINALIZED. */
+int gscl_init(int device, gscl_ctx **ctx);
+/* gscl_begin: enter the device-resident phase on `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  Reserves context scratch on first use.  Between
+ * begin and end the host must not touch grid memory (Section 4). */
+int gscl_begin(gscl_ctx *ctx, void *hip_stream);
+/* gscl_end: synchronize the stream and leave the phase; host reads are valid. */
+int gscl_end(gscl_ctx *ctx);
+/* gscl_finalize: release context scratch and the context (GSCL_Finalize). */
+int gscl_finalize(gscl_ctx *ctx);
+/* gscl_reserve: grow context scratch for launches of up to `max_points`
+ * interior points; call outside graph capture.  begin reserves 2^27 points. */
+int gscl_reserve(gscl_ctx *ctx, int64_t max_points);
+
+/* ---- grids ---------------------------------------------------------------- */
+/* Bytes of device memory a grid with this descriptor needs (0 if invalid). */
+size_t gscl_grid_bytes(const gscl_grid_desc *desc);
+/* Resolve default pitches into desc->pitch (in place).  Returns status. */
+int gscl_grid_layout(gscl_grid_desc *desc);
+/* Wrap caller-owned device memory (16-byte aligned, gscl_grid_bytes long). */
+int gscl_grid_create(gscl_ctx *ctx, const gscl_grid_desc *desc, void *dev_ptr,
+                     gscl_grid **out);
+int gscl_grid_destroy(gscl_grid *grid);
+
+/* ---- iteration spaces (Section 3) ----------------------------------------- */
+/* do_all: apply the operator at every interior point, in no particular order.
+ * Outputs may alias an input only if that input is read at offset 0 only.
+ * `fused` (nullable) reduces a per-point value in the same pass (Section 5.2
+ * fuse); its result goes to fused->dev_result if set, else to *fused_result
+ * (the call then synchronizes). */
+int gscl_do_all(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in, int n_in,
+                gscl_grid *const *out, int n_out, const gscl_reduce_desc *fused,
+                double *fused_result);
+/* do_reduce: reduce grid a (or a - b when b is non-NULL, same extents) over
+ * its interior with rd->op.  Accumulates in F64 (integers exactly). */
+int gscl_do_reduce(gscl_ctx *ctx, const gscl_reduce_desc *rd, const gscl_grid *a,
+                   const gscl_grid *b, double *result);
+
+/* ---- tile shapes (autotuning, Section 2 / Section 6 future work) ----------- */
+/* A tiled sweep runs blocks of NW waves; wave w owns one row of 64*V points of
+ * an x-by-y tile and the block marches cz planes (or layers) in z.  The
+ * library picks a shape from the extents; a tuner may override it for one
+ * (kind, dtype, extents) key of a context.  V in {1,2,4} (radius-2 kinds
+ * {1,2}; F64 {1,2}), NW in {4,8} (radius-2 kinds 4), cz >= 1. */
+typedef struct { int32_t V, NW, cz; } gscl_tile;
+int gscl_tile_get(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, gscl_tile *out);
+int gscl_tile_set(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, const gscl_tile *tile);
+int gscl_tile_clear(gscl_ctx *ctx);
+
+/* ---- HIP graphs of library launches --------------------------------------- */
+/* Capture every launch the context issues between the two calls into a graph
+ * (stream capture on the context stream).  No host-synchronizing call may be
+ * issued while capturing. */
+int gscl_graph_begin(gscl_ctx *ctx);
+int gscl_graph_end(gscl_ctx *ctx, gscl_graph **graph);
+int gscl_graph_launch(gscl_ctx *ctx, gscl_graph *graph);
+int gscl_graph_destroy(gscl_graph *graph);
+
+/* ---- solver (Section 5.2: do_all + fused convergence check until done) ---- */
+enum { GSCL_PREC_F64 = 0, GSCL_PREC_F32_IR = 1, GSCL_PREC_BF16_IR = 2, GSCL_PREC_F16_IR = 3 };
+typedef struct {
+    double omega;               /* Jacobi weight */
+    double h2;                  /* WJACOBI: grid spacing squared */
+    double kappa;               /* VC13: operator constant */
+    double rtol;                /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+    int32_t check_every;        /* sweeps per chunk (>= 2, even); the last sweep of
+                                   each chunk carries the residual check */
+    int32_t precision;          /* GSCL_PREC_* */
+    int32_t inner_sweeps;       /* IR: low-precision sweeps per outer step */
+    int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f) or
+                                   GSCL_K_VC13_APPLY (A x = b, several fields) */
+    int64_t max_sweeps;
+} gscl_solve_desc;
+typedef struct {
+    int64_t sweeps;             /* total sweeps (inner sweeps for IR) */
+    int64_t outer;              /* IR outer steps (0 for F64) */
+    double rel_residual;        /* last checked ||r||_2 / ||b||_2 (F64) */
+    double seconds;             /* wall time of the call */
+} gscl_solve_stats;
+/* Workspace bytes gscl_solve needs for this problem (caller allocates). */
+size_t gscl_solve_workspace_bytes(const gscl_solve_desc *sd, const gscl_grid *x, int nfields);
+/* Solve A x = b.  x: nfields solution grids (initial guess in, answer out),
+ * b: nfields right-hand sides, coef: the operator's coefficient grids (VC13:
+ * 10, WJACOBI: none).  F64 x/b.  Returns GSCL_ERR_NOCONV if max_sweeps is hit
+ * and GSCL_ERR_NUMERIC on a NaN residual. */
+int gscl_solve(gscl_ctx *ctx, const gscl_solve_desc *sd, gscl_grid *const *x,
+               const gscl_grid *const *b, int nfields, const gscl_grid *const *coef, int ncoef,
+               void *workspace, size_t workspace_bytes, gscl_solve_stats *stats);
+
+/* ---- batched multi-grid executor (many Poisson solves in one launch) ----- */
+/* A batch holds up to max_slots independent Poisson problems (WJACOBI, F64
+ * u/f, Dirichlet 0, any cube or box sizes) and sweeps all active ones with one
+ * persistent kernel per sweep.  Slot state lives in device memory, so a
+ * captured step graph stays valid while slots come and go.
+ *   precision GSCL_PREC_F64: ping-pong F64 sweeps, residual fused into the
+ *     last sweep of each step.
+ *   precision GSCL_PREC_F32_IR: F32 correction sweeps with an F64 residual /
+ *     update pass per step (iterative refinement).
+ * hbm_budget bounds the sum of admitted slot footprints (bytes). */
+typedef struct {
+    int32_t max_slots;
+    int32_t precision;
+    int32_t sweeps_per_step;    /* even, >= 2 */
+    int32_t use_graph;          /* capture each step once into a HIP graph */
+    double omega;
+    double rtol;
+    size_t hbm_budget;
+    int64_t max_sweeps;         /* per request; reaching it retires as not converged */
+} gscl_batch_desc;
+typedef struct {
+    int32_t state;              /* 0 free, 1 running, 2 converged, 3 failed */
+    int32_t reserved;
+    int64_t sweeps;
+    double rel_residual;
+} gscl_slot_stats;
+int gscl_batch_create(gscl_ctx *ctx, const gscl_batch_desc *bd, gscl_batch **out);
+/* Device bytes one request of extents n needs inside the batch (its
+ * footprint), including the caller's u and f. */
+size_t gscl_batch_footprint(const gscl_batch *b, const int64_t n[3]);
+/* Admit a problem: u (initial guess, answer on completion) and f, both F64
+ * ndim 3, h2 its spacing squared.  The library allocates the slot's private
+ * work grids from the device.  Returns GSCL_ERR_NOMEM when no slot is free or
+ * the footprint would exceed hbm_budget; the caller queues the request. */
+int gscl_batch_admit(gscl_batch *b, gscl_grid *u, const gscl_grid *f, double h2, int *slot);
+/* Run one step (sweeps_per_step sweeps over every running slot). Async. */
+int gscl_batch_step(gscl_batch *b);
+/* Copy slot states to the host (synchronizes) and list finished slots. */
+int gscl_batch_poll(gscl_batch *b, int *done, int cap, int *n_done);
+/* Release a finished (or running: cancel) slot; its answer is in its u grid. */
+int gscl_batch_retire(gscl_batch *b, int slot, gscl_slot_stats *stats);
+int gscl_batch_destroy(gscl_batch *b);
+
+/* ---- misc --------------------------------------------------------------- */
+const char *gscl_last_error(void);
+const char *gscl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSCL_H */

@@ -186,10 +186,17 @@ def poisson_solve(f, h2: float, omega: float, rtol: float, check_every: int,
 # --------------------------------------------------------------------------- #
 # Multi-grid variable-coefficient sweep (9 inputs, 3 outputs)
 # --------------------------------------------------------------------------- #
-def varcoef7_sweep(u, c: Sequence, s, bc=PERIODIC, bcv=0.0):
+def _pack(c) -> np.ndarray:
+    if isinstance(c, np.ndarray) and c.dtype == np.float64 and c.ndim == 4 and c.flags.c_contiguous:
+        return c
+    return np.ascontiguousarray(np.stack([_f64(x) for x in c]))
+
+
+def varcoef7_sweep(u, c, s, bc=PERIODIC, bcv=0.0):
+    """c: the 7 coefficient grids (a list, or one packed (7, nz, ny, nx) FP64 array)."""
     u = _f64(u)
     nz, ny, nx = u.shape
-    cp = np.ascontiguousarray(np.stack([_f64(x) for x in c]))
+    cp = _pack(c)
     sa = _f64(s)
     unew, r, fm = np.empty_like(u), np.empty_like(u), np.empty_like(u)
     lib().oracle_varcoef7(nx, ny, nz, _ptr(u), _ptr(cp), _ptr(sa), int(bc), float(bcv),
@@ -201,7 +208,7 @@ def varcoef7_run(u0, c, s, nsweeps: int, check_every: int, bc=PERIODIC):
     """nsweeps sweeps; the L2 norm of the residual grid written by sweeps
     check_every, 2*check_every, ... is recorded.  Returns (u, r, fmag, norms)."""
     u = _f64(u0)
-    cp = [_f64(x) for x in c]
+    cp = _pack(c)
     sa = _f64(s)
     norms = []
     r = fm = None

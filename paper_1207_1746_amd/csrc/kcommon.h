@@ -1,0 +1,163 @@
+// Device-side helpers shared by the gfx950 kernels: element conversions,
+// vector loads/stores, boundary synthesis, the XCD-aware tile order, and the
+// deterministic two-level reduction used by do_reduce and by fused sweeps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace gk {
+
+typedef __hip_bfloat16 bf16;
+typedef _Float16 f16;
+
+enum { BC_DIRICHLET = 0, BC_PERIODIC = 1, BC_CLAMP = 2 };
+enum { R_SUM = 0, R_SUMSQ = 1, R_L2 = 2, R_MAXABS = 3, R_ALL_LE = 4 };
+
+// ---- conversions: storage type -> compute type and back -----------------
+template <class T> __device__ __forceinline__ T from_s(double v) { return (T)v; }
+template <class T> __device__ __forceinline__ T from_s(float v) { return (T)v; }
+template <class T> __device__ __forceinline__ T from_s(f16 v) { return (T)(float)v; }
+template <class T> __device__ __forceinline__ T from_s(bf16 v) { return (T)__bfloat162float(v); }
+template <class T> __device__ __forceinline__ T from_s(uint8_t v) { return (T)v; }
+template <class T> __device__ __forceinline__ T from_s(int16_t v) { return (T)v; }
+template <class T> __device__ __forceinline__ T from_s(uint32_t v) { return (T)v; }
+
+template <class S> struct Store;
+template <> struct Store<double> {
+    template <class T> __device__ __forceinline__ static double cv(T v) { return (double)v; }
+};
+template <> struct Store<float> {
+    template <class T> __device__ __forceinline__ static float cv(T v) { return (float)v; }
+};
+template <> struct Store<f16> {
+    template <class T> __device__ __forceinline__ static f16 cv(T v) { return (f16)(float)v; }
+};
+template <> struct Store<bf16> {
+    template <class T> __device__ __forceinline__ static bf16 cv(T v) {
+        return __float2bfloat16((float)v);
+    }
+};
+
+// ---- vectors of V storage elements, loaded/stored as one access ---------
+template <class S, int V> struct alignas(sizeof(S) * V) Vec { S v[V]; };
+
+template <class S, int V>
+__device__ __forceinline__ Vec<S, V> vload(const S* p) {
+    return *reinterpret_cast<const Vec<S, V>*>(p);
+}
+template <class S, int V>
+__device__ __forceinline__ void vstore(S* p, const Vec<S, V>& x) {
+    *reinterpret_cast<Vec<S, V>*>(p) = x;
+}
+
+// ---- grid geometry shared by every kernel of one call --------------------
+struct Geo {
+    int nx, ny, nz;        // interior extents (nz = layers for 2D)
+    int64_t py, pz;        // row and plane pitch in elements
+    int bc;                // boundary rule of the neighbour-read grids
+    double bcv;            // Dirichlet value
+};
+
+__device__ __forceinline__ int wrap_idx(int i, int n, int bc) {
+    if (bc == BC_PERIODIC) {
+        int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Value at (x, y, z) with the boundary rule applied outside the interior.
+// For 2D layered grids pass the layer as z and keep it in range.
+template <class T, class S>
+__device__ __forceinline__ T fetch_bc(const S* base, const Geo& g, int x, int y, int z) {
+    if ((unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny &&
+        (unsigned)z < (unsigned)g.nz)
+        return from_s<T>(base[(int64_t)z * g.pz + (int64_t)y * g.py + x]);
+    if (g.bc == BC_DIRICHLET) return (T)g.bcv;
+    x = wrap_idx(x, g.nx, g.bc);
+    y = wrap_idx(y, g.ny, g.bc);
+    z = wrap_idx(z, g.nz, g.bc);
+    return from_s<T>(base[(int64_t)z * g.pz + (int64_t)y * g.py + x]);
+}
+
+// ---- XCD-aware block order ----------------------------------------------
+// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+// Remap so that each XCD receives one contiguous range of logical tiles:
+// neighbouring tiles then share halo rows/planes through the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int NX = 8;
+    int q = n / NX, r = n % NX;
+    int x = b % NX, k = b / NX;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ---- reductions ------------------------------------------------------------
+__device__ __forceinline__ double nanmax(double a, double b) {
+    return (b != b || b > a) ? b : a;  // NaN in b wins; NaN in a stays (b > NaN false)
+}
+__device__ __forceinline__ double red_acc(double acc, double v, int op) {
+    if (op == R_SUM) return acc + v;
+    if (op == R_SUMSQ || op == R_L2) return acc + v * v;
+    return nanmax(acc, fabs(v));  // MAXABS, ALL_LE
+}
+__device__ __forceinline__ double red_comb(double a, double b, int op) {
+    if (op == R_MAXABS || op == R_ALL_LE) return nanmax(a, b);
+    return a + b;
+}
+__device__ __forceinline__ double red_final(double v, int op, double eps) {
+    if (op == R_L2) return sqrt(v);
+    if (op == R_ALL_LE) return (v <= eps) ? 1.0 : 0.0;  // NaN -> 0
+    return v;
+}
+
+struct RedArgs {
+    double* partials;      // one slot per block
+    unsigned* ticket;      // zero between launches (reset by the last block)
+    double* result;        // final value (device)
+    int op;
+    double eps;
+};
+
+// Combine one double per thread over the block, store the block partial, and
+// let the last block to arrive fold all partials in block order.  The order of
+// every combination is fixed by the launch shape, so results are reproducible
+// run to run.  Must be called by every thread of the block.
+__device__ __forceinline__ void block_reduce_finish(double acc, const RedArgs& ra, int block,
+                                                    int nblocks) {
+    __shared__ double wpart[16];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc = red_comb(acc, __shfl_xor(acc, off, 64), ra.op);
+    if (lane == 0) wpart[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wpart[0];
+        for (int i = 1; i < nw; ++i) b = red_comb(b, wpart[i], ra.op);
+        ra.partials[block] = b;
+        __threadfence();
+        unsigned t = atomicAdd(ra.ticket, 1u);
+        last = (t == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double a = 0.0;  // identity of both + and max|.|
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) a = red_comb(a, ra.partials[i], ra.op);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a = red_comb(a, __shfl_xor(a, off, 64), ra.op);
+    __syncthreads();
+    if (lane == 0) wpart[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wpart[0];
+        for (int i = 1; i < nw; ++i) b = red_comb(b, wpart[i], ra.op);
+        *ra.result = red_final(b, ra.op, ra.eps);
+        atomicExch(ra.ticket, 0u);
+    }
+}
+
+}  // namespace gk

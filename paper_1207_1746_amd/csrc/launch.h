@@ -1,0 +1,67 @@
+// Host-side launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kcommon.h"
+#include "tiled.h"
+
+namespace gk {
+
+struct TileCfg {
+    int V;    // elements per lane along x
+    int NW;   // waves (rows) per block
+    int cz;   // z planes (or layers) per block
+};
+
+// Tiled sweeps.  `nblocks` receives the number of blocks launched (partials
+// needed by a fused reduction).  Return hipErrorInvalidValue for a
+// configuration without an instantiated kernel.
+hipError_t launch_wjacobi(TArgs& a, int dtype, int ndim, bool has_f, const TileCfg& c, bool red,
+                          hipStream_t s, int* nblocks);
+hipError_t launch_varcoef7(TArgs& a, int dtype, const TileCfg& c, bool red, hipStream_t s,
+                           int* nblocks);
+hipError_t launch_vc13_apply(TArgs& a, int dtype, int nfields, const TileCfg& c, bool red,
+                             hipStream_t s, int* nblocks);
+hipError_t launch_vc13_jacobi(TArgs& a, int dtype_nb, int dtype_g, int dtype_c, int nfields,
+                              const TileCfg& c, bool red, hipStream_t s, int* nblocks);
+hipError_t launch_vc13_resid(TArgs& a, int dtype_c, int nfields, const TileCfg& c, bool red,
+                             hipStream_t s, int* nblocks);
+// Blocks a tiled launch with this configuration would use.
+int tiled_blocks(const Geo& g, const TileCfg& c);
+
+// Generic linear operator (any offsets, per-grid boundary rule).
+struct LinTerm {
+    int out, grid, dx, dy, dz, coef;
+    double w;
+};
+struct LArgs {
+    Geo g;                 // extents and pitches (bc fields unused)
+    int ndim;
+    int nin, nout, nterms;
+    int bc[16];
+    double bcv[16];
+    const void* in[16];
+    void* out[8];
+    LinTerm t[64];
+    int operand;
+    RedArgs ra;
+};
+hipError_t launch_linear(LArgs& a, int dtype, bool red, hipStream_t s, int* nblocks);
+
+// Standalone reduction of a (or a - b) over the interior.
+hipError_t launch_reduce(const void* a, const void* b, int dtype, const Geo& g, RedArgs ra,
+                         hipStream_t s, int max_blocks, int* nblocks);
+
+// Integer image filters: box 5x5 (rounded mean) and 3x3 Laplacian.
+hipError_t launch_image(const uint8_t* img, uint8_t* box, int16_t* lap, const Geo& g,
+                        int lap_kind, hipStream_t s);
+
+// Elementwise y = alpha * a + beta * b (b optional) with per-grid storage
+// types; and fill.  Used by the iterative-refinement driver.
+hipError_t launch_axpby(void* y, int ty, const void* a, int ta, double alpha, const void* b, int tb,
+                        double beta, const Geo& g, hipStream_t s);
+hipError_t launch_fill(void* y, int ty, double value, const Geo& g, hipStream_t s);
+
+}  // namespace gk

@@ -1,0 +1,49 @@
+// Launch helpers shared by the sweep instantiation units.
+#pragma once
+#include "launch.h"
+#include "ops.h"
+
+namespace gk {
+
+enum { DT_F64 = 0, DT_F32 = 1, DT_F16 = 2, DT_BF16 = 3 };
+
+template <class Op, int V, int NW>
+static hipError_t run(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nblocks) {
+    a.ntx = (a.g.nx + 64 * V - 1) / (64 * V);
+    a.nty = (a.g.ny + NW - 1) / NW;
+    a.cz = c.cz;
+    a.ncz = (a.g.nz + c.cz - 1) / c.cz;
+    const int n = a.ntx * a.nty * a.ncz;
+    *nblocks = n;
+    if (n == 0) return hipSuccess;
+    if (red)
+        hipLaunchKernelGGL((tiled_sweep<Op, V, NW, true>), dim3(n), dim3(64 * NW), 0, s, a);
+    else
+        hipLaunchKernelGGL((tiled_sweep<Op, V, NW, false>), dim3(n), dim3(64 * NW), 0, s, a);
+    return hipGetLastError();
+}
+
+// (V, NW) shapes instantiated for the 7-point family.
+template <class Op>
+static hipError_t run7(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
+    constexpr bool wide = sizeof(typename Op::T) <= 4;  // 16-byte vectors: V=4 (F32) or V=2 (F64)
+    if (c.V == 1 && c.NW == 4) return run<Op, 1, 4>(a, c, red, s, nb);
+    if (c.V == 1 && c.NW == 8) return run<Op, 1, 8>(a, c, red, s, nb);
+    if (c.V == 2 && c.NW == 4) return run<Op, 2, 4>(a, c, red, s, nb);
+    if (c.V == 2 && c.NW == 8) return run<Op, 2, 8>(a, c, red, s, nb);
+    if constexpr (wide) {
+        if (c.V == 4 && c.NW == 4) return run<Op, 4, 4>(a, c, red, s, nb);
+        if (c.V == 4 && c.NW == 8) return run<Op, 4, 8>(a, c, red, s, nb);
+    }
+    return hipErrorInvalidValue;
+}
+
+// (V, NW) shapes instantiated for the 13-point family (radius 2).
+template <class Op>
+static hipError_t run13(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
+    if (c.V == 1 && c.NW == 4) return run<Op, 1, 4>(a, c, red, s, nb);
+    if (c.V == 2 && c.NW == 4) return run<Op, 2, 4>(a, c, red, s, nb);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gk

@@ -1,0 +1,275 @@
+// Tiled do_all driver for gfx950: one block owns an x-by-y tile of the grid
+// and marches it through a chunk of z planes.
+//
+//   * wave w of the block owns row y0 + w; lane l owns V consecutive x points
+//     (x0 + l*V ...), loaded as one vector access (unit-stride, coalesced).
+//   * grids read at offsets ("neighbour-read", the operator's access traits):
+//     each is kept as a register queue of 2R+1 z planes per lane, and the
+//     current plane is staged in LDS with its x and y halo for the in-plane
+//     neighbours.  Every input plane is therefore fetched from HBM once per
+//     sweep (plus a thin halo).
+//   * pointwise grids are streamed straight into registers.
+//   * the next plane's loads are issued before the current plane is computed
+//     (one plane of software prefetch).
+//   * halo values outside the domain are synthesized from the boundary rule
+//     (no stored halo, no halo-fill pass).
+//   * an optional fused reduction of a per-point value (Section 5.2 fuse) is
+//     accumulated in FP64 registers and finished by the last block.
+#pragma once
+
+#include "kcommon.h"
+
+namespace gk {
+
+struct TArgs {
+    Geo g;
+    const void* nb[5];     // neighbour-read grids
+    const void* pa[10];    // pointwise group A
+    const void* pb[10];    // pointwise group B
+    void* out[5];
+    double p[8];           // operator parameters
+    int ntx, nty, ncz, cz; // tile counts and z chunk length
+    int operand;           // fused reduction operand selector
+    RedArgs ra;
+};
+
+template <class T, int NF, int R>
+struct Star {
+    T c[NF];
+    T xm[NF][R], xp[NF][R], ym[NF][R], yp[NF][R], zm[NF][R], zp[NF][R];
+};
+
+template <int N> struct AtLeast1 { static constexpr int v = N > 0 ? N : 1; };
+
+// Load V elements of row (y, z) starting at gx, boundary-synthesized where
+// any element falls outside the interior.
+template <class T, class S, int V>
+__device__ __forceinline__ void load_nb(const S* base, const Geo& g, int gx, int y, int z,
+                                        T (&o)[V]) {
+    const bool row_in = (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
+    if (row_in && gx >= 0 && gx + V <= g.nx) {
+        Vec<S, V> v = vload<S, V>(base + (int64_t)z * g.pz + (int64_t)y * g.py + gx);
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = from_s<T>(v.v[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = fetch_bc<T, S>(base, g, gx + i, y, z);
+    }
+}
+
+// Pointwise row load; only rows/columns inside the interior are meaningful.
+// Rows are padded to 16 elements, so a vector starting inside the row stays
+// inside the allocation.
+template <class S, int V>
+__device__ __forceinline__ void load_pw(const S* base, const Geo& g, int gx, int y, int z,
+                                        S (&o)[V]) {
+    if ((unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz && gx < g.nx) {
+        Vec<S, V> v = vload<S, V>(base + (int64_t)z * g.pz + (int64_t)y * g.py + gx);
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = v.v[i];
+    }
+}
+
+template <class Op, int V, int NW, bool RED>
+__global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
+    using T = typename Op::T;
+    using SN = typename Op::SN;
+    using SA = typename Op::SA;
+    using SB = typename Op::SB;
+    using SO = typename Op::SO;
+    constexpr int NF = Op::NF, NO = Op::NO, NR = Op::NR, R = Op::R;
+    constexpr int NA = AtLeast1<Op::NA>::v, NB = AtLeast1<Op::NB>::v;
+    constexpr int RZ = Op::NDIM == 3 ? R : 0;
+    constexpr int QD = 2 * RZ + 1;
+    constexpr int TX = 64 * V;
+    constexpr int CO = (16 / (int)sizeof(T)) > R ? (16 / (int)sizeof(T)) : R;  // aligned core column
+    constexpr int LW = CO + TX + R;
+    constexpr int LH = NW + 2 * R;
+    static_assert(NW >= 2 * R, "need a wave per halo row");
+
+    __shared__ __attribute__((aligned(16))) T lds[NF][LH][LW];
+
+    const Geo& g = a.g;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ntiles = a.ntx * a.nty * a.ncz;
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const int xt = tile % a.ntx;
+    const int rest = tile / a.ntx;
+    const int yt = rest % a.nty;
+    const int zc = rest / a.nty;
+    const int x0 = xt * TX, y0 = yt * NW, z0 = zc * a.cz;
+    const int z1 = min(z0 + a.cz, g.nz);
+    const int gx = x0 + lane * V, gy = y0 + w;
+    const int hy = (w < R) ? (y0 - R + w) : (y0 + NW + (w - R));
+    const int hrow = (w < R) ? w : (NW + w);
+    const bool has_halo_row = w < 2 * R;
+    const int ccol = CO + lane * V;
+
+    T q[NF][QD][V];
+    T qn[NF][V];
+    T xh[NF][2 * R], xhn[NF][2 * R];
+    T yh[NF][V], yhn[NF][V];
+    SA pa[NA][V], pan[NA][V];
+    SB pb[NB][V], pbn[NB][V];
+
+    auto load_halo = [&](int z, T (&xo)[NF][2 * R], T (&yo)[NF][V]) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const SN* b = static_cast<const SN*>(a.nb[f]);
+            if (lane == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) xo[f][r] = fetch_bc<T, SN>(b, g, x0 - R + r, gy, z);
+            }
+            if (lane == 63) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) xo[f][R + r] = fetch_bc<T, SN>(b, g, x0 + TX + r, gy, z);
+            }
+            if (has_halo_row) load_nb<T, SN, V>(b, g, gx, hy, z, yo[f]);
+        }
+    };
+    auto load_point = [&](int z, SA (&ao)[NA][V], SB (&bo)[NB][V]) {
+#pragma unroll
+        for (int i = 0; i < Op::NA; ++i) load_pw<SA, V>(static_cast<const SA*>(a.pa[i]), g, gx, gy, z, ao[i]);
+#pragma unroll
+        for (int i = 0; i < Op::NB; ++i) load_pw<SB, V>(static_cast<const SB*>(a.pb[i]), g, gx, gy, z, bo[i]);
+    };
+
+    // warm-up: planes z0-RZ .. z0+RZ, halos and pointwise values of plane z0
+#pragma unroll
+    for (int s = 0; s < QD; ++s)
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            load_nb<T, SN, V>(static_cast<const SN*>(a.nb[f]), g, gx, gy, z0 - RZ + s, q[f][s]);
+    load_halo(z0, xh, yh);
+    load_point(z0, pa, pb);
+
+    double acc = 0.0;
+    const bool row_ok = gy < g.ny;
+
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 1 < z1;
+        if (more) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                load_nb<T, SN, V>(static_cast<const SN*>(a.nb[f]), g, gx, gy, z + RZ + 1, qn[f]);
+            load_halo(z + 1, xhn, yhn);
+            load_point(z + 1, pan, pbn);
+        }
+        // stage plane z in LDS: core row, x halo (edge lanes), y halo rows
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) lds[f][R + w][ccol + v] = q[f][RZ][v];
+            if (lane == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[f][R + w][CO - R + r] = xh[f][r];
+            }
+            if (lane == 63) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[f][R + w][CO + TX + r] = xh[f][R + r];
+            }
+            if (has_halo_row) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) lds[f][hrow][ccol + v] = yh[f][v];
+            }
+        }
+        __syncthreads();
+
+        T res[NO][V];
+        double redv[NR][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            Star<T, NF, R> st;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                st.c[f] = q[f][RZ][v];
+#pragma unroll
+                for (int r = 1; r <= R; ++r) {
+                    st.xm[f][r - 1] = (v - r >= 0) ? q[f][RZ][(v - r) >= 0 ? v - r : 0]
+                                                   : lds[f][R + w][ccol + v - r];
+                    st.xp[f][r - 1] = (v + r < V) ? q[f][RZ][(v + r) < V ? v + r : 0]
+                                                  : lds[f][R + w][ccol + v + r];
+                    st.ym[f][r - 1] = lds[f][R + w - r][ccol + v];
+                    st.yp[f][r - 1] = lds[f][R + w + r][ccol + v];
+                    if (RZ > 0) {
+                        st.zm[f][r - 1] = q[f][(RZ - r) >= 0 ? RZ - r : 0][v];
+                        st.zp[f][r - 1] = q[f][(RZ + r) < QD ? RZ + r : 0][v];
+                    } else {
+                        st.zm[f][r - 1] = T(0);
+                        st.zp[f][r - 1] = T(0);
+                    }
+                }
+            }
+            T av[NA], bv[NB], o[NO];
+            double rv[NR];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) av[i] = Op::NA > 0 ? from_s<T>(pa[i][v]) : T(0);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) bv[i] = Op::NB > 0 ? from_s<T>(pb[i][v]) : T(0);
+            Op::apply(st, av, bv, a.p, o, rv, a.operand);
+#pragma unroll
+            for (int i = 0; i < NO; ++i) res[i][v] = o[i];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) redv[i][v] = rv[i];
+        }
+        // store outputs (vector when the whole vector is inside the row)
+        if (row_ok) {
+            const int64_t off = (int64_t)z * g.pz + (int64_t)gy * g.py + gx;
+            if (gx + V <= g.nx) {
+#pragma unroll
+                for (int i = 0; i < NO; ++i) {
+                    Vec<SO, V> vv;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) vv.v[v] = Store<SO>::cv(res[i][v]);
+                    vstore<SO, V>(static_cast<SO*>(a.out[i]) + off, vv);
+                }
+                if (RED) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+#pragma unroll
+                        for (int i = 0; i < NR; ++i) acc = red_acc(acc, redv[i][v], a.ra.op);
+                }
+            } else if (gx < g.nx) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (gx + v < g.nx) {
+#pragma unroll
+                        for (int i = 0; i < NO; ++i)
+                            static_cast<SO*>(a.out[i])[off + v] = Store<SO>::cv(res[i][v]);
+                        if (RED) {
+#pragma unroll
+                            for (int i = 0; i < NR; ++i) acc = red_acc(acc, redv[i][v], a.ra.op);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+#pragma unroll
+                for (int s = 0; s + 1 < QD; ++s)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) q[f][s][v] = q[f][s + 1][v];
+#pragma unroll
+                for (int v = 0; v < V; ++v) q[f][QD - 1][v] = qn[f][v];
+#pragma unroll
+                for (int r = 0; r < 2 * R; ++r) xh[f][r] = xhn[f][r];
+#pragma unroll
+                for (int v = 0; v < V; ++v) yh[f][v] = yhn[f][v];
+            }
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int v = 0; v < V; ++v) pa[i][v] = pan[i][v];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int v = 0; v < V; ++v) pb[i][v] = pbn[i][v];
+        }
+    }
+    if (RED) block_reduce_finish(acc, a.ra, tile, ntiles);
+}
+
+}  // namespace gk
