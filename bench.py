@@ -1,0 +1,352 @@
+#!/usr/bin/env python3
+"""Benchmark of the stencil hot path on one MI355X.
+
+Default workload: the multi-grid variable-coefficient sweep -- 256^3 FP32,
+7-point operator with 7 coefficient grids, a source grid and the field (9
+input grids), writing 3 output grids (new u, residual, flux magnitude),
+periodic boundaries, 100 sweeps with the L2 norm of the residual fused into
+every 10th sweep.  One step = those 100 sweeps (and 10 reductions, whose
+results stay on the device).  Inputs are resident in HBM before timing.
+
+Prints one JSON line with Gpts/s (value), algorithmic HBM GB/s and its
+fraction of the 8 TB/s peak for the dominant kernel (HIP events around every
+sweep of the timed region), and a CPU baseline: the FP64 oracle on the host
+cores over a bounded sample of the same workload.
+
+Other workloads (--config) print the same fields for development use.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stencil Gpts/s + HBM GB/s vs peak; batched solves/s with p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1207_1746_amd/csrc/tiled.h", "paper_1207_1746_amd/csrc/ops.h",
+                  "paper_1207_1746_amd/csrc/kcommon.h", "paper_1207_1746_amd/csrc/sweeps_common.h",
+                  "paper_1207_1746_amd/csrc/k_image.hip", "paper_1207_1746_amd/csrc/k_sweep_varcoef.hip",
+                  "paper_1207_1746_amd/csrc/k_sweep_wjacobi.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str, per_launch_bytes_alg: float):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data.get(workload_key)
+        if not rec or rec.get("kernel_hash") != kernel_hash():
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------- #
+# workloads
+# --------------------------------------------------------------------------- #
+class VarCoef:
+    key = "varcoef7_256_f32"
+    bytes_per_point = 48  # read u, c0..c6, s (9 x 4 B), write u', r, |F| (3 x 4 B)
+
+    def __init__(self, ctx, n=256, sweeps=100, every=10):
+        import torch
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G = G
+        self.n, self.sweeps, self.every = n, sweeps, every
+        u, c, s = W.varcoef_grids(n)
+        self.host = (u, c, s)
+        shp = (n, n, n)
+        self.gu = ctx.grid(shp, G.F32, halo=1, bc=G.PERIODIC, data=u)
+        self.gu2 = ctx.grid(shp, G.F32, halo=1, bc=G.PERIODIC)
+        self.gc = [ctx.grid(shp, G.F32, halo=0, data=x) for x in c]
+        self.gs = ctx.grid(shp, G.F32, halo=0, data=s)
+        self.gr = ctx.grid(shp, G.F32, halo=0)
+        self.gf = ctx.grid(shp, G.F32, halo=0)
+        self.norms = torch.zeros(sweeps // every, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        self.points = n ** 3
+        self.units_per_step = self.points * sweeps
+        self.unit = "Gpts/s"
+
+    def step(self, ev=None):
+        G = self.G
+        ping = (self.gu, self.gu2)
+        for k in range(1, self.sweeps + 1):
+            src, dst = ping[(k - 1) % 2], ping[k % 2]
+            red = k % self.every == 0
+            if ev is not None and not red:
+                ev.begin()
+            self.ctx.do_all(G.K_VARCOEF7, [src] + self.gc + [self.gs], [dst, self.gr, self.gf],
+                            reduce=(G.R_L2, G.RV_RESIDUAL) if red else None,
+                            dev_result=self.norms[k // self.every - 1] if red else None)
+            if ev is not None and not red:
+                ev.end()
+
+    def config(self):
+        return {"workload": f"multi-grid variable-coefficient 7-point sweep, {self.n}^3 FP32, "
+                            "9 input grids (u, c0..c6, s) -> 3 outputs (u', r, |F|), periodic, "
+                            f"{self.sweeps} sweeps, fused L2(r) every {self.every}",
+                "grid": [self.n] * 3, "sweeps_per_step": self.sweeps, "reduce_every": self.every,
+                "launch": "tiled z-march, tile " + str(self.ctx.tile_get(self.G.K_VARCOEF7, self.gu))}
+
+    def cpu_baseline(self, budget_s=12.0):
+        import numpy as np
+        import oracle
+        u, c, s = self.host
+        x = u.astype(np.float64)
+        cp = np.ascontiguousarray(np.stack([ci.astype(np.float64) for ci in c]))
+        sd = s.astype(np.float64)
+        t0 = time.perf_counter()
+        done = 0
+        while done < self.sweeps:
+            x, r, _ = oracle.varcoef7_sweep(x, cp, sd)
+            done += 1
+            if done % self.every == 0:
+                oracle.sumsq(r)
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * done / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"FP64 oracle, first {done} of the {self.sweeps} sweeps on the same "
+                          f"{self.n}^3 inputs ({dt:.1f} s), residual norms every {self.every}"}
+
+
+class Jacobi:
+    key = "wjacobi_f64"
+    bytes_per_point = 16
+
+    def __init__(self, ctx, n=64, sweeps=10):
+        import torch
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G = G
+        self.n, self.sweeps = n, sweeps
+        u0, self.h2 = W.jacobi_cube(n)
+        self.host = u0
+        self.a = ctx.grid(u0.shape, G.F64, halo=1, data=u0)
+        self.b = ctx.grid(u0.shape, G.F64, halo=1)
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        self.points = n ** 3
+        self.units_per_step = self.points * sweeps
+        self.unit = "Gpts/s"
+
+    def step(self, ev=None):
+        G = self.G
+        for k in range(self.sweeps):
+            src, dst = (self.a, self.b) if k % 2 == 0 else (self.b, self.a)
+            last = k == self.sweeps - 1
+            if ev is not None and not last:
+                ev.begin()
+            self.ctx.do_all(G.K_WJACOBI, [src], [dst], p=(1.0, self.h2),
+                            reduce=(G.R_L2, G.RV_UPDATE) if last else None,
+                            dev_result=self.res if last else None)
+            if ev is not None and not last:
+                ev.end()
+
+    def config(self):
+        return {"workload": f"Jacobi 7-point {self.n}^3 FP64, Dirichlet 0, {self.sweeps} sweeps + L2 of update",
+                "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.jacobi_run(self.host, self.sweeps, None, 1.0, self.h2)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.units_per_step * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} full runs of the workload in {dt:.1f} s"}
+
+
+class Image:
+    key = "image_8192_u8"
+    bytes_per_point = 4  # read 1 B, write 1 B box + 2 B Laplacian
+
+    def __init__(self, ctx, n=8192, planes=4):
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G = G
+        img = W.image_planes(n, n, planes)
+        self.host = img
+        self.gi = ctx.grid(img.shape, G.U8, halo=2, bc=G.CLAMP, ndim=2, data=img)
+        self.gb = ctx.grid(img.shape, G.U8, halo=0, ndim=2)
+        self.gl = ctx.grid(img.shape, G.I16, halo=0, ndim=2)
+        self.ctx = ctx
+        self.points = n * n * planes
+        self.units_per_step = self.points
+        self.unit = "Gpx/s"
+        self.n, self.planes = n, planes
+
+    def step(self, ev=None):
+        if ev is not None:
+            ev.begin()
+        self.ctx.do_all(self.G.K_IMG_BOX5_LAP, [self.gi], [self.gb, self.gl], p=(4,))
+        if ev is not None:
+            ev.end()
+
+    def config(self):
+        return {"workload": f"5x5 box + 3x3 Laplacian, {self.planes} x {self.n}^2 uint8, clamp"}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.img(self.host[:1], 4)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.n * self.n * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} single planes in {dt:.1f} s"}
+
+
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image}
+
+
+class KernelEvents:
+    """HIP events bracketing every launch of the dominant kernel, on the stream
+    the library launches on (the context's stream)."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.pairs = []
+        self._open = None
+
+    def begin(self):
+        import torch
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self._open = e
+
+    def end(self):
+        import torch
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self.pairs.append((self._open, e))
+
+    def mean_ms(self):
+        ts = [a.elapsed_time(b) for a, b in self.pairs]
+        return sum(ts) / len(ts) if ts else float("nan"), len(ts)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="varcoef", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--tile", default=None, help="V,NW,cz override for the dominant kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1207_1746_amd as G
+    ctx = G.Context(0)
+    wl = WORKLOADS[args.config](ctx)
+    if args.tile:
+        V, NW, cz = (int(v) for v in args.tile.split(","))
+        kind = {"varcoef": G.K_VARCOEF7, "jacobi": G.K_WJACOBI}.get(args.config)
+        if kind is not None:
+            ctx.tile_set(kind, wl.gu if args.config == "varcoef" else wl.a, (V, NW, cz))
+    stream = ctx.stream
+
+    for _ in range(args.warmup):
+        wl.step()
+    sync()
+    ev = KernelEvents(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        wl.step(ev)
+    sync()
+    t1 = time.perf_counter()
+    sec = t1 - t0
+    ms_per_step = sec / args.steps * 1e3
+    value = wl.units_per_step * args.steps / sec / 1e9
+    kmean_ms, nk = ev.mean_ms()
+    per_launch_bytes = wl.bytes_per_point * wl.points
+    achieved = per_launch_bytes / (kmean_ms * 1e-3) / 1e9
+    traffic = measured_traffic(wl.key, per_launch_bytes)
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        sync()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": wl.unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "image": "u8"}[args.config],
+        "data": "synthetic (seeded)",
+        "config": wl.config(),
+        "hbm_gbs_step": round(per_launch_bytes * wl.units_per_step / wl.points * args.steps / sec / 1e9, 2)
+        if args.config != "image" else round(per_launch_bytes * args.steps / sec / 1e9, 2),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel_ms": round(kmean_ms, 5),
+            "launches_timed": nk,
+            "alg_bytes_per_launch": per_launch_bytes,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = wl.cpu_baseline()
+    ctx.end()
+    ctx.finalize()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

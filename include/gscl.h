@@ -131,7 +131,10 @@ typedef struct gscl_batch gscl_batch;
  *   p[0] = kappa, p[1] = omega, p[2] = F.  Storage as VC13_APPLY.
  * GSCL_K_VC13_RESID: in = {x_0..x_{F-1} (F64), b_0..b_{F-1} (F64), c0..c9
  *   (any float storage)}, out = {r_f} (F32): r = b - A x in F64, stored F32.
- *   Fused operands: RESIDUAL (r in F64).                                    */
+ *   Fused operands: RESIDUAL (r in F64).
+ * GSCL_K_POISSON_RESID: in = {x (F64), f (F64)}, out = {r (F32)}:
+ *   r = f - (S - 6 x)/h^2 computed in F64, stored F32 (ndim 3); p[1] = h^2.
+ *   Fused operand RESIDUAL = r (F64).                                       */
 enum {
     GSCL_K_LINEAR = 0,
     GSCL_K_WJACOBI = 1,
@@ -139,7 +142,8 @@ enum {
     GSCL_K_IMG_BOX5_LAP = 3,
     GSCL_K_VC13_APPLY = 4,
     GSCL_K_VC13_JACOBI = 5,
-    GSCL_K_VC13_RESID = 6
+    GSCL_K_VC13_RESID = 6,
+    GSCL_K_POISSON_RESID = 7
 };
 
 typedef struct {

@@ -25,7 +25,8 @@ OK, ERR_ARG, ERR_STATE, ERR_SHAPE, ERR_HALO, ERR_ALIAS, ERR_DTYPE, ERR_NOMEM, ER
     ERR_HIP, ERR_NUMERIC, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11
 F64, F32, F16, BF16, U8, I16, U32 = range(7)
 DIRICHLET, PERIODIC, CLAMP = 0, 1, 2
-K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_VC13_RESID = range(7)
+K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_VC13_RESID, \
+    K_POISSON_RESID = range(8)
 R_SUM, R_SUMSQ, R_L2, R_MAXABS, R_ALL_LE = range(5)
 RV_OUT0, RV_UPDATE, RV_RESIDUAL = range(3)
 PREC_F64, PREC_F32_IR, PREC_BF16_IR, PREC_F16_IR = range(4)
@@ -341,6 +342,28 @@ class Context:
                                    ctypes.byref(res)), "gscl_do_reduce")
         return res.value if dev_result is None else None
 
+    # solver ---------------------------------------------------------------------
+    def solve(self, kind: int, x: Sequence[Grid], b: Sequence[Grid], coef: Sequence[Grid] = (),
+              omega: float = 6 / 7, h2: float = 1.0, kappa: float = 0.25, rtol: float = 1e-8,
+              check_every: int = 32, precision: int = PREC_F64, inner_sweeps: int = 64,
+              max_sweeps: int = 10 ** 7) -> dict:
+        """gscl_solve; returns {'sweeps', 'outer', 'rel_residual', 'seconds'}."""
+        torch = _torch()
+        sd = SolveDesc(omega, h2, kappa, rtol, check_every, precision, inner_sweeps, kind, max_sweeps)
+        hx, nx_ = _handles(x)
+        hb, _ = _handles(b)
+        hc, nc = _handles(coef) if coef else (None, 0)
+        nbytes = lib().gscl_solve_workspace_bytes(ctypes.byref(sd), x[0].handle, nx_)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        st = SolveStats()
+        check(lib().gscl_solve(self.handle, ctypes.byref(sd), hx, hb, nx_, hc, nc, _vp(ws.data_ptr()),
+                               nbytes, ctypes.byref(st)), "gscl_solve")
+        return {"sweeps": st.sweeps, "outer": st.outer, "rel_residual": st.rel_residual,
+                "seconds": st.seconds}
+
+    def batch(self, **kw) -> "Batch":
+        return Batch(self, **kw)
+
     # tiles and graphs -------------------------------------------------------------
     def tile_get(self, kind: int, g: Grid) -> tuple:
         t = Tile()
@@ -374,6 +397,60 @@ class Graph:
     def close(self):
         if self.handle:
             lib().gscl_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched multi-grid Poisson executor (gscl_batch_*)."""
+
+    def __init__(self, ctx: Context, max_slots: int = 64, precision: int = PREC_F64,
+                 sweeps_per_step: int = 32, use_graph: bool = True, omega: float = 6 / 7,
+                 rtol: float = 1e-8, hbm_budget: int = 8 << 30, max_sweeps: int = 10 ** 7):
+        self.ctx = ctx
+        bd = BatchDesc(max_slots, precision, sweeps_per_step, int(use_graph), omega, rtol, hbm_budget,
+                       max_sweeps)
+        h = _vp()
+        check(lib().gscl_batch_create(ctx.handle, ctypes.byref(bd), ctypes.byref(h)), "gscl_batch_create")
+        self.handle = h
+        self.max_slots = max_slots
+        self.sweeps_per_step = sweeps_per_step
+
+    def footprint(self, shape) -> int:
+        n = (_i64 * 3)(shape[2], shape[1], shape[0])
+        return int(lib().gscl_batch_footprint(self.handle, n))
+
+    def admit(self, u: Grid, f: Grid, h2: float) -> int | None:
+        """Slot id, or None when no slot / budget is free (the caller queues)."""
+        slot = ctypes.c_int(-1)
+        rc = lib().gscl_batch_admit(self.handle, u.handle, f.handle, float(h2), ctypes.byref(slot))
+        if rc == ERR_NOMEM:
+            return None
+        check(rc, "gscl_batch_admit")
+        return slot.value
+
+    def step(self):
+        check(lib().gscl_batch_step(self.handle), "gscl_batch_step")
+
+    def poll(self) -> list[int]:
+        arr = (ctypes.c_int * self.max_slots)()
+        n = ctypes.c_int(0)
+        check(lib().gscl_batch_poll(self.handle, arr, self.max_slots, ctypes.byref(n)), "gscl_batch_poll")
+        return [arr[i] for i in range(min(n.value, self.max_slots))]
+
+    def retire(self, slot: int) -> dict:
+        st = SlotStats()
+        check(lib().gscl_batch_retire(self.handle, slot, ctypes.byref(st)), "gscl_batch_retire")
+        return {"state": st.state, "sweeps": st.sweeps, "rel_residual": st.rel_residual}
+
+    def close(self):
+        if self.handle:
+            lib().gscl_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -134,7 +134,6 @@ extern "C" int gscl_init(int device, gscl_ctx** out) {
     c->stream = nullptr;
     c->partials = nullptr;
     c->partial_cap = 0;
-    c->ticket = nullptr;
     c->result = nullptr;
     c->capturing = false;
     *out = c;
@@ -161,9 +160,7 @@ extern "C" int gscl_begin(gscl_ctx* c, void* stream) {
     if (c->state == CTX_FINALIZED) return gscl_fail(GSCL_ERR_STATE, "context finalized");
     GSCL_HIP(hipSetDevice(c->device));
     c->stream = (hipStream_t)stream;
-    if (!c->ticket) {
-        GSCL_HIP(hipMalloc(&c->ticket, 64 * sizeof(unsigned)));
-        GSCL_HIP(hipMemset(c->ticket, 0, 64 * sizeof(unsigned)));
+    if (!c->result) {
         GSCL_HIP(hipMalloc(&c->result, 64 * sizeof(double)));
         GSCL_HIP(hipMemset(c->result, 0, 64 * sizeof(double)));
         int rc = ensure_partials(c, 1 << 16);
@@ -193,10 +190,9 @@ extern "C" int gscl_end(gscl_ctx* c) {
 extern "C" int gscl_finalize(gscl_ctx* c) {
     if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
     if (c->state == CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "gscl_finalize inside begin/end");
-    if (c->ticket) {
+    if (c->result) {
         hipSetDevice(c->device);
         hipFree(c->partials);
-        hipFree(c->ticket);
         hipFree(c->result);
     }
     c->magic = 0;
@@ -336,7 +332,6 @@ static int check_dtypes(gscl_grid* const* g, int first, int count, int dt, const
 
 static void fill_red(gscl_ctx* c, const gscl_reduce_desc* rd, gk::RedArgs& ra) {
     ra.partials = c->partials;
-    ra.ticket = c->ticket;
     ra.result = rd && rd->dev_result ? (double*)rd->dev_result : c->result;
     ra.op = rd ? rd->op : 0;
     ra.eps = rd ? rd->eps : 0.0;
@@ -453,6 +448,26 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
                 fill_red(c, fused, a.ra);
             }
             he = gk::launch_wjacobi(a, dt, g0->d.ndim, n_in == 2, t, red, c->stream, &nblocks);
+            break;
+        }
+        case GSCL_K_POISSON_RESID: {
+            if (n_in != 2 || n_out != 1) return gscl_fail(GSCL_ERR_ARG, "POISSON_RESID takes {x, f} -> {r}");
+            if ((rc = check_dtypes(in, 0, 2, GSCL_F64, "input")) || (rc = check_dtypes(out, 0, 1, GSCL_F32, "output")))
+                return rc;
+            if ((rc = check_nb(in, 0, 1, 1, out, n_out, 3))) return rc;
+            if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "POISSON_RESID needs h^2 != 0 in p[1]");
+            double p[8] = {0.0, op->p[1], 1.0 / op->p[1], 0, 0, 0, 0, 0};
+            fill_targs(a, g0, p);
+            a.nb[0] = in[0]->ptr;
+            a.pa[0] = in[1]->ptr;
+            a.out[0] = out[0]->ptr;
+            a.operand = red ? fused->operand : 0;
+            gk::TileCfg t = pick_tile(c, GSCL_K_WJACOBI, GSCL_F64, g0->d);
+            if (red) {
+                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra);
+            }
+            he = gk::launch_poisson_resid(a, t, red, c->stream, &nblocks);
             break;
         }
         case GSCL_K_VARCOEF7: {

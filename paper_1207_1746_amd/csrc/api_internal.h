@@ -19,7 +19,6 @@ struct gscl_ctx {
     hipStream_t stream;
     double* partials;      // per-block reduction partials
     int64_t partial_cap;   // doubles
-    unsigned* ticket;      // last-block ticket (zero between launches)
     double* result;        // device slots for reduction results
     bool capturing;
     std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, gk::TileCfg> tiles;

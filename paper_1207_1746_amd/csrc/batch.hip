@@ -1,0 +1,561 @@
+// Batched executor: many independent Poisson problems (Lap_h u = f, zero
+// Dirichlet boundary, any box sizes) swept together.
+//
+// * A device slot table lists the admitted problems, each with its tile range
+//   in one global tile list (prefix sums).  A persistent kernel with a fixed
+//   grid walks the global list, finds each tile's slot, and runs the same
+//   tiled z-march as do_all on that slot's grids.  Tile shapes depend only on
+//   a slot's own extents, and each slot's residual partials are folded in
+//   tile order by a per-slot finish block: a result is bit-identical whether
+//   the problem runs alone or among others.
+// * The finish block also applies the stopping rule and freezes a slot that
+//   converged (or failed) so later sweeps skip it; the answer stays in the
+//   caller's u grid.
+// * The table lives in device memory and the kernels take only its address,
+//   so one step is captured once as a HIP graph and replayed while problems
+//   come and go.  Work grids come from one arena reserved at creation; the
+//   step path never allocates.
+// * F64 mode: ping-pong F64 sweeps; the last sweep of a step also reduces the
+//   residual of its input (the fused check of Section 5.2).
+// * F32 refinement mode: per step an F64 residual pass (stored F32) with its
+//   norm and the stopping rule, sweeps_per_step F32 correction sweeps from
+//   d = 0, then u += d (and d reset to 0) in F64.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "api_internal.h"
+#include "ops.h"
+
+namespace {
+
+constexpr int BV = 1, BNW = 4;  // tile shape of the batched kernels (64 x 4 points)
+
+struct BSlot {
+    int id;                  // index into the state array
+    int nx, ny, nz;
+    int64_t py, pz;
+    double h2, ih2;
+    double* u;
+    double* u2;
+    const double* f;
+    float* d;
+    float* d2;
+    float* rh;
+    int ntx, nty, ncz, cz;
+    int tile_begin, ntiles;
+};
+
+struct BState {
+    int state;               // 0 free, 1 running, 2 converged, 3 failed
+    int checks;
+    double res2;
+    double fnorm2;
+    double pad;
+};
+
+struct BHeader {
+    int nslots;
+    int total_tiles;
+};
+
+enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2 };
+
+__device__ __forceinline__ int find_slot(const BSlot* __restrict__ s, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int MODE, bool RED>
+__global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict__ slots, const BState* st,
+                                                        const BHeader* hdr, double* partials, int parity,
+                                                        double omega) {
+    using OpF64 = gk::OpWJacobi<double, double, 3, true>;
+    using OpF32 = gk::OpWJacobi<float, float, 3, true>;
+    const int n = hdr->nslots, total = hdr->total_tiles;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int si = find_slot(slots, n, t);
+        const BSlot& s = slots[si];
+        if (st[s.id].state != 1) continue;
+        gk::TArgs a;
+        a.g.nx = s.nx;
+        a.g.ny = s.ny;
+        a.g.nz = s.nz;
+        a.g.py = s.py;
+        a.g.pz = s.pz;
+        a.g.bc = gk::BC_DIRICHLET;
+        a.g.bcv = 0.0;
+        a.ntx = s.ntx;
+        a.nty = s.nty;
+        a.ncz = s.ncz;
+        a.cz = s.cz;
+        a.p[0] = omega;
+        a.p[1] = s.h2;
+        a.p[2] = s.ih2;
+        a.operand = gk::RV_RESIDUAL;
+        a.ra.partials = partials;
+        a.ra.result = nullptr;
+        a.ra.op = gk::R_SUMSQ;
+        a.ra.eps = 0.0;
+        const int local = t - s.tile_begin;
+        double acc = 0.0;
+        if (MODE == MODE_F64) {
+            a.nb[0] = parity ? s.u2 : s.u;
+            a.out[0] = parity ? s.u : s.u2;
+            a.pa[0] = s.f;
+            gk::sweep_tile<OpF64, BV, BNW, RED>(a, local, acc);
+        } else if (MODE == MODE_RESID) {
+            a.nb[0] = s.u;
+            a.pa[0] = s.f;
+            a.out[0] = s.rh;
+            gk::sweep_tile<gk::OpPoissonResid, BV, BNW, RED>(a, local, acc);
+        } else {
+            a.nb[0] = parity ? s.d2 : s.d;
+            a.out[0] = parity ? s.d : s.d2;
+            a.pa[0] = s.rh;
+            gk::sweep_tile<OpF32, BV, BNW, false>(a, local, acc);
+        }
+        if (RED) gk::block_reduce(acc, a.ra, t);
+    }
+}
+
+// u += d and d = 0 over every tile of running slots (refinement update).
+__global__ __launch_bounds__(64 * BNW) void batch_update(const BSlot* __restrict__ slots, const BState* st,
+                                                         const BHeader* hdr) {
+    const int n = hdr->nslots, total = hdr->total_tiles;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int si = find_slot(slots, n, t);
+        const BSlot& s = slots[si];
+        if (st[s.id].state != 1) continue;
+        const int local = t - s.tile_begin;
+        const int xt = local % s.ntx, rest = local / s.ntx, yt = rest % s.nty, zc = rest / s.nty;
+        const int x = xt * 64 + lane, y = yt * BNW + w;
+        if (x >= s.nx || y >= s.ny) continue;
+        const int z1 = min(zc * s.cz + s.cz, s.nz);
+        for (int z = zc * s.cz; z < z1; ++z) {
+            const int64_t p = (int64_t)z * s.pz + (int64_t)y * s.py + x;
+            s.u[p] = s.u[p] + (double)s.d[p];
+            s.d[p] = 0.0f;
+        }
+    }
+}
+
+// Per-slot fold of the residual partials and the stopping rule.
+__global__ __launch_bounds__(256) void batch_finish(const BSlot* __restrict__ slots, BState* st,
+                                                    const BHeader* hdr, const double* partials, double rtol2,
+                                                    int sweeps_per_check, long long max_sweeps, int ir) {
+    const int i = blockIdx.x;
+    if (i >= hdr->nslots) return;
+    const BSlot& s = slots[i];
+    BState& b = st[s.id];
+    if (b.state != 1) return;
+    double a = 0.0;
+    for (int k = threadIdx.x; k < s.ntiles; k += blockDim.x) a += partials[s.tile_begin + k];
+    __shared__ double wp[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double v = ((wp[0] + wp[1]) + wp[2]) + wp[3];
+        b.checks += 1;
+        b.res2 = v;
+        const long long done = (long long)(ir ? b.checks - 1 : b.checks) * sweeps_per_check;
+        if (v != v)
+            b.state = 3;
+        else if (v <= rtol2 * b.fnorm2)
+            b.state = 2;
+        else if (done >= max_sweeps)
+            b.state = 3;
+    }
+}
+
+__global__ void batch_state_init(BState* st, int id) {
+    if (threadIdx.x == 0) {
+        st[id].state = 1;
+        st[id].checks = 0;
+        st[id].res2 = 0.0;
+    }
+}
+
+// ---- arena: first-fit allocator over one device reservation -------------
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t used = 0;
+    void init(char* b, size_t n) {
+        base = b;
+        size = n;
+        free_.clear();
+        free_[0] = n;
+        used = 0;
+    }
+    char* alloc(size_t n) {
+        n = (n + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > n) free_[off + n] = len - n;
+                used += n;
+                return base + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(char* p, size_t n) {
+        n = (n + 255) / 256 * 256;
+        size_t off = (size_t)(p - base);
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct gscl_batch {
+    uint32_t magic;
+    gscl_ctx* ctx;
+    gscl_batch_desc desc;
+    Arena arena;
+    char* arena_mem;
+    BSlot* d_slots;
+    BState* d_state;
+    BHeader* d_hdr;
+    double* d_partials;
+    int64_t partial_cap;
+    BSlot* h_slots;     // pinned staging
+    BState* h_state;    // pinned
+    BHeader* h_hdr;     // pinned
+    hipEvent_t upload_done;
+    std::vector<bool> used;
+    std::vector<BSlot> slot;       // by id
+    std::vector<size_t> work_bytes;
+    std::vector<char*> work_ptr;
+    std::vector<size_t> foot;
+    size_t footprint_used;
+    bool dirty;
+    gscl_graph* graph;
+    int persist_blocks;
+};
+
+static size_t slot_work_bytes(int precision, const gscl_grid_desc& d) {
+    const size_t pts = (size_t)d.pitch[1] * (size_t)d.n[2];
+    const size_t r = [](size_t v) { return (v + 255) / 256 * 256; }(pts * 8);
+    const size_t r4 = (pts * 4 + 255) / 256 * 256;
+    return precision == GSCL_PREC_F64 ? r : 3 * r4;
+}
+
+extern "C" size_t gscl_batch_footprint(const gscl_batch* b, const int64_t n[3]) {
+    if (!b || b->magic != BATCH_MAGIC || !n) return 0;
+    gscl_grid_desc d{};
+    d.ndim = 3;
+    d.n[0] = n[0];
+    d.n[1] = n[1];
+    d.n[2] = n[2];
+    d.dtype = GSCL_F64;
+    if (gscl_grid_layout(&d)) return 0;
+    return 2 * gscl_grid_bytes(&d) + slot_work_bytes(b->desc.precision, d);
+}
+
+extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_batch** out) {
+    if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
+    if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "batch needs an active context");
+    if (!bd || !out) return gscl_fail(GSCL_ERR_ARG, "null argument");
+    if (bd->max_slots < 1 || bd->max_slots > 4096) return gscl_fail(GSCL_ERR_ARG, "max_slots must be 1..4096");
+    if (bd->precision != GSCL_PREC_F64 && bd->precision != GSCL_PREC_F32_IR)
+        return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch precision must be F64 or F32_IR");
+    if (bd->sweeps_per_step < 2 || bd->sweeps_per_step % 2)
+        return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be even and >= 2");
+    if (!(bd->rtol > 0) || bd->max_sweeps < 1 || bd->hbm_budget < 4096)
+        return gscl_fail(GSCL_ERR_ARG, "rtol, max_sweeps and hbm_budget must be positive");
+    gscl_batch* b = new gscl_batch();
+    b->magic = BATCH_MAGIC;
+    b->ctx = c;
+    b->desc = *bd;
+    const int ms = bd->max_slots;
+    auto fail = [&](hipError_t e, const char* w) {
+        gscl_hip_fail(e, w);
+        hipFree(b->arena_mem);
+        hipFree(b->d_slots);
+        hipFree(b->d_state);
+        hipFree(b->d_hdr);
+        hipFree(b->d_partials);
+        hipHostFree(b->h_slots);
+        hipHostFree(b->h_state);
+        hipHostFree(b->h_hdr);
+        delete b;
+        return GSCL_ERR_HIP;
+    };
+    hipError_t e;
+    // the library's work grids of admitted problems share one arena; they are
+    // at most half of a problem's footprint (u, f are the caller's)
+    const size_t arena = (bd->hbm_budget / 2 + 255) / 256 * 256;
+    if ((e = hipMalloc(&b->arena_mem, arena)) != hipSuccess) return fail(e, "hipMalloc(arena)");
+    b->arena.init(b->arena_mem, arena);
+    if ((e = hipMalloc(&b->d_slots, sizeof(BSlot) * ms)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->d_state, sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->d_hdr, sizeof(BHeader))) != hipSuccess) return fail(e, "hipMalloc");
+    b->partial_cap = 1 << 16;
+    if ((e = hipMalloc(&b->d_partials, sizeof(double) * b->partial_cap)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&b->h_slots, sizeof(BSlot) * ms)) != hipSuccess) return fail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&b->h_state, sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipHostMalloc");
+    if ((e = hipHostMalloc(&b->h_hdr, sizeof(BHeader))) != hipSuccess) return fail(e, "hipHostMalloc");
+    if ((e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
+    if ((e = hipMemset(b->d_state, 0, sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipMemset");
+    memset(b->h_hdr, 0, sizeof(BHeader));
+    if ((e = hipMemcpy(b->d_hdr, b->h_hdr, sizeof(BHeader), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "hipMemcpy");
+    b->used.assign(ms, false);
+    b->slot.assign(ms, BSlot{});
+    b->work_bytes.assign(ms, 0);
+    b->work_ptr.assign(ms, nullptr);
+    b->foot.assign(ms, 0);
+    b->footprint_used = 0;
+    b->dirty = false;
+    b->graph = nullptr;
+    b->persist_blocks = 1024;
+    *out = b;
+    return GSCL_OK;
+}
+
+static bool batch_ok(const gscl_batch* b) { return b && b->magic == BATCH_MAGIC; }
+
+// Rebuild the compact table (admitted slots in id order, tile prefix sums) and
+// upload it on the context stream.
+static int upload_table(gscl_batch* b) {
+    gscl_ctx* c = b->ctx;
+    GSCL_HIP(hipEventSynchronize(b->upload_done));  // staging buffers free again
+    int n = 0, tiles = 0;
+    for (int id = 0; id < b->desc.max_slots; ++id) {
+        if (!b->used[id]) continue;
+        BSlot s = b->slot[id];
+        s.tile_begin = tiles;
+        tiles += s.ntiles;
+        b->h_slots[n++] = s;
+    }
+    if (tiles > b->partial_cap) {
+        // grow the partials (invalidates a captured step graph)
+        GSCL_HIP(hipStreamSynchronize(c->stream));
+        GSCL_HIP(hipFree(b->d_partials));
+        b->partial_cap = std::max<int64_t>(tiles, 2 * b->partial_cap);
+        GSCL_HIP(hipMalloc(&b->d_partials, sizeof(double) * b->partial_cap));
+        if (b->graph) {
+            gscl_graph_destroy(b->graph);
+            b->graph = nullptr;
+        }
+    }
+    b->h_hdr->nslots = n;
+    b->h_hdr->total_tiles = tiles;
+    if (n) GSCL_HIP(hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(BSlot) * n, hipMemcpyHostToDevice, c->stream));
+    GSCL_HIP(hipMemcpyAsync(b->d_hdr, b->h_hdr, sizeof(BHeader), hipMemcpyHostToDevice, c->stream));
+    GSCL_HIP(hipEventRecord(b->upload_done, c->stream));
+    b->dirty = false;
+    return GSCL_OK;
+}
+
+extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f, double h2, int* slot) {
+    if (!batch_ok(b) || !slot) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
+    gscl_ctx* c = b->ctx;
+    if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "batch needs an active context");
+    if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "admit inside graph capture");
+    if (!grid_ok(u) || !grid_ok(f)) return gscl_fail(GSCL_ERR_ARG, "invalid grid");
+    if (u->d.dtype != GSCL_F64 || f->d.dtype != GSCL_F64) return gscl_fail(GSCL_ERR_DTYPE, "batch needs F64 u and f");
+    if (u->d.ndim != 3 || memcmp(u->d.n, f->d.n, sizeof u->d.n) || u->d.pitch[0] != f->d.pitch[0] ||
+        u->d.pitch[1] != f->d.pitch[1])
+        return gscl_fail(GSCL_ERR_SHAPE, "u and f must be 3D with equal extents and pitches");
+    if (u->d.pitch[0] % 16) return gscl_fail(GSCL_ERR_SHAPE, "row pitch must be a multiple of 16 elements");
+    if (u->d.halo < 1) return gscl_fail(GSCL_ERR_HALO, "u must declare halo >= 1");
+    if (!(h2 > 0)) return gscl_fail(GSCL_ERR_ARG, "h2 must be positive");
+    if (u->d.n[0] * u->d.n[1] * u->d.n[2] == 0) return gscl_fail(GSCL_ERR_SHAPE, "empty grid");
+    int id = -1;
+    for (int i = 0; i < b->desc.max_slots; ++i)
+        if (!b->used[i]) {
+            id = i;
+            break;
+        }
+    if (id < 0) return gscl_fail(GSCL_ERR_NOMEM, "no free slot");
+    const size_t wb = slot_work_bytes(b->desc.precision, u->d);
+    const size_t fp = wb + u->bytes + f->bytes;
+    if (b->footprint_used + fp > b->desc.hbm_budget)
+        return gscl_fail(GSCL_ERR_NOMEM, "HBM budget exhausted (%zu + %zu > %zu bytes)", b->footprint_used, fp,
+                         b->desc.hbm_budget);
+    char* mem = b->arena.alloc(wb);
+    if (!mem) return gscl_fail(GSCL_ERR_NOMEM, "HBM budget exhausted (%zu of %zu bytes in use)", b->arena.used,
+                               b->arena.size);
+    BSlot s{};
+    s.id = id;
+    s.nx = (int)u->d.n[0];
+    s.ny = (int)u->d.n[1];
+    s.nz = (int)u->d.n[2];
+    s.py = u->d.pitch[0];
+    s.pz = u->d.pitch[1];
+    s.h2 = h2;
+    s.ih2 = 1.0 / h2;
+    s.u = (double*)u->ptr;
+    s.f = (const double*)f->ptr;
+    const size_t pts = (size_t)s.pz * (size_t)s.nz;
+    if (b->desc.precision == GSCL_PREC_F64) {
+        s.u2 = (double*)mem;
+    } else {
+        const size_t r4 = (pts * 4 + 255) / 256 * 256;
+        s.d = (float*)mem;
+        s.d2 = (float*)(mem + r4);
+        s.rh = (float*)(mem + 2 * r4);
+    }
+    s.cz = std::min(8, s.nz);
+    s.ntx = (s.nx + 64 * BV - 1) / (64 * BV);
+    s.nty = (s.ny + BNW - 1) / BNW;
+    s.ncz = (s.nz + s.cz - 1) / s.cz;
+    s.ntiles = s.ntx * s.nty * s.ncz;
+    b->slot[id] = s;
+    b->used[id] = true;
+    b->work_ptr[id] = mem;
+    b->work_bytes[id] = wb;
+    b->foot[id] = fp;
+    b->footprint_used += fp;
+    // state: running, ||f||^2 on the device, d = 0 for refinement
+    hipLaunchKernelGGL(batch_state_init, dim3(1), dim3(64), 0, c->stream, b->d_state, id);
+    GSCL_HIP(hipGetLastError());
+    gscl_reduce_desc rd{GSCL_R_SUMSQ, 0, 0.0, &b->d_state[id].fnorm2};
+    int rc = gscl_do_reduce(c, &rd, f, nullptr, nullptr);
+    if (rc) return rc;
+    if (b->desc.precision != GSCL_PREC_F64) {
+        gk::Geo g = geo_of(u);
+        GSCL_HIP(gk::launch_fill(s.d, GSCL_F32, 0.0, g, c->stream));
+    }
+    b->dirty = true;
+    *slot = id;
+    return GSCL_OK;
+}
+
+static int enqueue_step(gscl_batch* b) {
+    gscl_ctx* c = b->ctx;
+    hipStream_t s = c->stream;
+    const int S = b->desc.sweeps_per_step;
+    const double rtol2 = b->desc.rtol * b->desc.rtol;
+    const dim3 grid(b->persist_blocks), blk(64 * BNW);
+    const int ms = b->desc.max_slots;
+    if (b->desc.precision == GSCL_PREC_F64) {
+        for (int k = 1; k <= S; ++k) {
+            const int parity = (k - 1) & 1;
+            if (k < S)
+                hipLaunchKernelGGL((batch_sweep<MODE_F64, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, parity, b->desc.omega);
+            else
+                hipLaunchKernelGGL((batch_sweep<MODE_F64, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, parity, b->desc.omega);
+        }
+        hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
+                           rtol2, S, (long long)b->desc.max_sweeps, 0);
+    } else {
+        hipLaunchKernelGGL((batch_sweep<MODE_RESID, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                           b->d_partials, 0, b->desc.omega);
+        hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
+                           rtol2, S, (long long)b->desc.max_sweeps, 1);
+        for (int k = 1; k <= S; ++k)
+            hipLaunchKernelGGL((batch_sweep<MODE_F32, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                               b->d_partials, (k - 1) & 1, b->desc.omega);
+        hipLaunchKernelGGL(batch_update, grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr);
+    }
+    GSCL_HIP(hipGetLastError());
+    return GSCL_OK;
+}
+
+extern "C" int gscl_batch_step(gscl_batch* b) {
+    if (!batch_ok(b)) return gscl_fail(GSCL_ERR_ARG, "invalid batch");
+    gscl_ctx* c = b->ctx;
+    if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "batch needs an active context");
+    int rc;
+    if (b->dirty && (rc = upload_table(b))) return rc;
+    if (!b->desc.use_graph || !c->stream) return enqueue_step(b);
+    if (!b->graph) {
+        if ((rc = gscl_graph_begin(c))) return rc;
+        int e = enqueue_step(b);
+        gscl_graph* g = nullptr;
+        int e2 = gscl_graph_end(c, &g);
+        if (e) return e;
+        if (e2) return e2;
+        b->graph = g;
+    }
+    return gscl_graph_launch(c, b->graph);
+}
+
+extern "C" int gscl_batch_poll(gscl_batch* b, int* done, int cap, int* n_done) {
+    if (!batch_ok(b) || !n_done || (cap > 0 && !done)) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
+    gscl_ctx* c = b->ctx;
+    if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "poll inside graph capture");
+    const int ms = b->desc.max_slots;
+    GSCL_HIP(hipMemcpyAsync(b->h_state, b->d_state, sizeof(BState) * ms, hipMemcpyDeviceToHost, c->stream));
+    GSCL_HIP(hipStreamSynchronize(c->stream));
+    int n = 0;
+    for (int id = 0; id < ms; ++id)
+        if (b->used[id] && b->h_state[id].state >= 2) {
+            if (n < cap) done[n] = id;
+            ++n;
+        }
+    *n_done = n;
+    return GSCL_OK;
+}
+
+extern "C" int gscl_batch_retire(gscl_batch* b, int id, gscl_slot_stats* st) {
+    if (!batch_ok(b) || id < 0 || id >= b->desc.max_slots) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
+    if (!b->used[id]) return gscl_fail(GSCL_ERR_ARG, "slot %d is not admitted", id);
+    gscl_ctx* c = b->ctx;
+    if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "retire inside graph capture");
+    // make sure no queued step still touches the slot's grids
+    GSCL_HIP(hipStreamSynchronize(c->stream));
+    BState bs;
+    GSCL_HIP(hipMemcpy(&bs, &b->d_state[id], sizeof bs, hipMemcpyDeviceToHost));
+    if (st) {
+        st->state = bs.state;
+        st->reserved = 0;
+        const int ir = b->desc.precision != GSCL_PREC_F64;
+        st->sweeps = (int64_t)(ir ? std::max(bs.checks - 1, 0) : bs.checks) * b->desc.sweeps_per_step;
+        st->rel_residual = bs.fnorm2 > 0 ? sqrt(bs.res2 / bs.fnorm2) : 0.0;
+    }
+    b->arena.release(b->work_ptr[id], b->work_bytes[id]);
+    b->footprint_used -= b->foot[id];
+    b->used[id] = false;
+    b->dirty = true;
+    return GSCL_OK;
+}
+
+extern "C" int gscl_batch_destroy(gscl_batch* b) {
+    if (!batch_ok(b)) return gscl_fail(GSCL_ERR_ARG, "invalid batch");
+    hipStreamSynchronize(b->ctx->stream);
+    if (b->graph) gscl_graph_destroy(b->graph);
+    hipEventDestroy(b->upload_done);
+    hipFree(b->arena_mem);
+    hipFree(b->d_slots);
+    hipFree(b->d_state);
+    hipFree(b->d_hdr);
+    hipFree(b->d_partials);
+    hipHostFree(b->h_slots);
+    hipHostFree(b->h_state);
+    hipHostFree(b->h_hdr);
+    b->magic = 0;
+    delete b;
+    return GSCL_OK;
+}

@@ -42,9 +42,8 @@ __global__ __launch_bounds__(256) void linear_kernel(LArgs a) {
         }
     }
     if (RED) {
-        const int nblk = gridDim.x * gridDim.y * gridDim.z;
         const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_reduce_finish(acc, a.ra, b, nblk);
+        block_reduce(acc, a.ra, b);
     }
 }
 
@@ -61,7 +60,9 @@ hipError_t launch_linear(LArgs& a, int dtype, bool red, hipStream_t s, int* nblo
     } else {
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !red) return e;
+    return launch_reduce_finish(a.ra, *nblocks, s);
 }
 
 }  // namespace gk

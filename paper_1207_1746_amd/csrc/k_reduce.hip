@@ -1,7 +1,7 @@
 // do_reduce (Section 3): combine a per-point value over the interior with a
 // commutative operator.  Each wave walks whole rows with unit-stride vector
 // loads, accumulates in FP64 (integer grids exactly), and the block partials
-// are folded in block order by the last block to finish.
+// are folded in block order by a one-block finish kernel.
 #include "launch.h"
 
 namespace gk {
@@ -37,7 +37,30 @@ __global__ __launch_bounds__(256) void reduce_kernel(const S* __restrict__ a,
             }
         }
     }
-    block_reduce_finish(acc, ra, blockIdx.x, gridDim.x);
+    block_reduce(acc, ra, blockIdx.x);
+}
+
+// One block folds the partials: thread t sums partials t, t+1024, ... in
+// order, then a fixed tree combines the threads.
+__global__ __launch_bounds__(1024) void reduce_finish(RedArgs ra, int n) {
+    double a = 0.0;  // identity of both + and max|.|
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a = red_comb(a, ra.partials[i], ra.op);
+    __shared__ double wpart[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a = red_comb(a, __shfl_xor(a, off, 64), ra.op);
+    if (lane == 0) wpart[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wpart[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = red_comb(b, wpart[i], ra.op);
+        *ra.result = red_final(b, ra.op, ra.eps);
+    }
+}
+
+hipError_t launch_reduce_finish(const RedArgs& ra, int n, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_finish, dim3(1), dim3(1024), 0, s, ra, n);
+    return hipGetLastError();
 }
 
 template <class S, int V>
@@ -49,7 +72,9 @@ static hipError_t go(const void* a, const void* b, const Geo& g, RedArgs ra, hip
     else
         hipLaunchKernelGGL((reduce_kernel<S, V, false>), dim3(nblk), dim3(256), 0, s,
                            static_cast<const S*>(a), static_cast<const S*>(b), g, ra);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_finish(ra, nblk, s);
 }
 
 hipError_t launch_reduce(const void* a, const void* b, int dtype, const Geo& g, RedArgs ra,

@@ -29,4 +29,8 @@ hipError_t launch_wjacobi(TArgs& a, int dtype, int ndim, bool has_f, const TileC
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_poisson_resid(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
+    return run7<OpPoissonResid>(a, c, red, s, nb);
+}
+
 }  // namespace gk

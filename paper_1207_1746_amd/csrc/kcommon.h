@@ -114,20 +114,18 @@ __device__ __forceinline__ double red_final(double v, int op, double eps) {
 
 struct RedArgs {
     double* partials;      // one slot per block
-    unsigned* ticket;      // zero between launches (reset by the last block)
     double* result;        // final value (device)
     int op;
     double eps;
 };
 
-// Combine one double per thread over the block, store the block partial, and
-// let the last block to arrive fold all partials in block order.  The order of
-// every combination is fixed by the launch shape, so results are reproducible
-// run to run.  Must be called by every thread of the block.
-__device__ __forceinline__ void block_reduce_finish(double acc, const RedArgs& ra, int block,
-                                                    int nblocks) {
+// Combine one double per thread over the block and store the block partial.
+// The partials are folded by a separate one-block finish kernel launched
+// right after (stream order makes them visible): no inter-block fence or
+// atomic is needed, which matters on a chip whose per-XCD L2s are not
+// coherent with each other.  Must be called by every thread of the block.
+__device__ __forceinline__ void block_reduce(double acc, const RedArgs& ra, int block) {
     __shared__ double wpart[16];
-    __shared__ int last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -138,25 +136,6 @@ __device__ __forceinline__ void block_reduce_finish(double acc, const RedArgs& r
         double b = wpart[0];
         for (int i = 1; i < nw; ++i) b = red_comb(b, wpart[i], ra.op);
         ra.partials[block] = b;
-        __threadfence();
-        unsigned t = atomicAdd(ra.ticket, 1u);
-        last = (t == (unsigned)(nblocks - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double a = 0.0;  // identity of both + and max|.|
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) a = red_comb(a, ra.partials[i], ra.op);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a = red_comb(a, __shfl_xor(a, off, 64), ra.op);
-    __syncthreads();
-    if (lane == 0) wpart[w] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = wpart[0];
-        for (int i = 1; i < nw; ++i) b = red_comb(b, wpart[i], ra.op);
-        *ra.result = red_final(b, ra.op, ra.eps);
-        atomicExch(ra.ticket, 0u);
     }
 }
 

@@ -50,6 +50,9 @@ struct LArgs {
 };
 hipError_t launch_linear(LArgs& a, int dtype, bool red, hipStream_t s, int* nblocks);
 
+// Fold `n` block partials in index order into ra.result (one block).
+hipError_t launch_reduce_finish(const RedArgs& ra, int n, hipStream_t s);
+
 // Standalone reduction of a (or a - b) over the interior.
 hipError_t launch_reduce(const void* a, const void* b, int dtype, const Geo& g, RedArgs ra,
                          hipStream_t s, int max_blocks, int* nblocks);
@@ -64,4 +67,10 @@ hipError_t launch_axpby(void* y, int ty, const void* a, int ta, double alpha, co
                         double beta, const Geo& g, hipStream_t s);
 hipError_t launch_fill(void* y, int ty, double value, const Geo& g, hipStream_t s);
 
+}  // namespace gk
+
+namespace gk {
+// Poisson residual r = f - Lap_h x (F64 math, F32 output) with optional fused
+// sum of squares of r.
+hipError_t launch_poisson_resid(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nblocks);
 }  // namespace gk

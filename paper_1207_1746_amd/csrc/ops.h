@@ -43,6 +43,27 @@ struct OpWJacobi {
     }
 };
 
+// Residual of the Poisson problem Lap_h x = f in FP64, stored as F32 (the
+// right-hand side of the low-precision correction sweeps of iterative
+// refinement): r = f - (S - 6 x) / h^2.  p[2] = 1/h^2.
+struct OpPoissonResid {
+    using T = double; using SN = double; using SA = double; using SB = double; using SO = float;
+    static constexpr int NF = 1, NA = 1, NB = 0, NO = 1, NR = 1, R = 1, NDIM = 3;
+    template <class ST, class AV, class BV>
+    __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
+                                                 const double* p, double (&o)[1], double (&rv)[1],
+                                                 int) {
+        double s = st.xp[0][0] + st.xm[0][0];
+        s = s + st.yp[0][0];
+        s = s + st.ym[0][0];
+        s = s + st.zp[0][0];
+        s = s + st.zm[0][0];
+        const double r = av[0] - (s - 6.0 * st.c[0]) * p[2];
+        o[0] = r;
+        rv[0] = r;
+    }
+};
+
 // Variable-coefficient 7-point operator over 9 input grids writing 3 outputs.
 //   pointwise A = c0..c6, s.  out = {u', r, |F|}.
 template <class T_, class S_>

@@ -1,19 +1,326 @@
-// gscl_solve: placeholder until the solver driver lands.
+// gscl_solve: the iteration of Section 5.2 -- apply the sweep, check
+// convergence with a reduction fused into the sweep, repeat -- as a library
+// call, plus mixed-precision iterative refinement.
+//
+//   F64:  weighted Jacobi x <- x + omega D^-1 (b - A x) in F64.  Chunks of
+//         `check_every` sweeps are captured once as a HIP graph; the last
+//         sweep of a chunk also reduces ||b - A x||^2 of its input, and the
+//         chunk's result is that sweep's output (the fused-check semantics of
+//         Section 5.2).  One device-to-host scalar per chunk.
+//   IR:   outer F64 residual r = b - A x (F64 math, stored F32) with its norm;
+//         inner `inner_sweeps` weighted-Jacobi sweeps of A d = r / sigma from
+//         d = 0 in low-precision storage (F32 math); x <- x + sigma d in F64.
+//         Only the residual and the update touch F64 data.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
 #include "api_internal.h"
 
-extern "C" size_t gscl_solve_workspace_bytes(const gscl_solve_desc*, const gscl_grid*, int) { return 0; }
-extern "C" int gscl_solve(gscl_ctx*, const gscl_solve_desc*, gscl_grid* const*, const gscl_grid* const*, int,
-                          const gscl_grid* const*, int, void*, size_t, gscl_solve_stats*) {
-    return gscl_fail(GSCL_ERR_UNSUPPORTED, "gscl_solve not built yet");
+namespace {
+
+struct TmpGrid {
+    gscl_grid g;
+};
+
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t bytes_like(const gscl_grid_desc& d, int dtype) {
+    return round256((size_t)d.pitch[1] * (size_t)std::max<int64_t>(d.n[2], 1) * dtype_size(dtype));
 }
-extern "C" int gscl_batch_create(gscl_ctx*, const gscl_batch_desc*, gscl_batch**) {
-    return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet");
+
+// Carve a grid with x's extents and pitches and another dtype from the workspace.
+gscl_grid* carve(gscl_ctx* c, const gscl_grid_desc& like, int dtype, int halo, char*& cur,
+                 std::vector<gscl_grid*>& keep) {
+    gscl_grid* g = new gscl_grid();
+    g->magic = GRID_MAGIC;
+    g->ctx = c;
+    g->d = like;
+    g->d.dtype = dtype;
+    g->d.halo = halo;
+    g->d.bc = GSCL_BC_DIRICHLET;
+    g->d.bc_value = 0.0;
+    g->ptr = cur;
+    g->bytes = bytes_like(like, dtype);
+    cur += g->bytes;
+    keep.push_back(g);
+    return g;
 }
-extern "C" size_t gscl_batch_footprint(const gscl_batch*, const int64_t*) { return 0; }
-extern "C" int gscl_batch_admit(gscl_batch*, gscl_grid*, const gscl_grid*, double, int*) {
-    return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet");
+
+int inner_dtype(int precision) {
+    switch (precision) {
+        case GSCL_PREC_F32_IR: return GSCL_F32;
+        case GSCL_PREC_BF16_IR: return GSCL_BF16;
+        case GSCL_PREC_F16_IR: return GSCL_F16;
+    }
+    return GSCL_F64;
 }
-extern "C" int gscl_batch_step(gscl_batch*) { return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet"); }
-extern "C" int gscl_batch_poll(gscl_batch*, int*, int, int*) { return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet"); }
-extern "C" int gscl_batch_retire(gscl_batch*, int, gscl_slot_stats*) { return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet"); }
-extern "C" int gscl_batch_destroy(gscl_batch*) { return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch not built yet"); }
+
+struct Cleanup {
+    std::vector<gscl_grid*> grids;
+    gscl_graph* graph = nullptr;
+    hipStream_t restore_stream = nullptr;
+    gscl_ctx* ctx = nullptr;
+    bool swapped = false;
+    ~Cleanup() {
+        if (graph) gscl_graph_destroy(graph);
+        for (auto* g : grids) {
+            g->magic = 0;
+            delete g;
+        }
+        if (swapped && ctx) ctx->stream = restore_stream;
+    }
+};
+
+}  // namespace
+
+extern "C" size_t gscl_solve_workspace_bytes(const gscl_solve_desc* sd, const gscl_grid* x, int nf) {
+    if (!sd || !grid_ok(x) || nf < 1) return 0;
+    const gscl_grid_desc& d = x->d;
+    if (sd->precision == GSCL_PREC_F64) return bytes_like(d, GSCL_F64) * nf + 256;
+    const int s = inner_dtype(sd->precision);
+    if (sd->kind == GSCL_K_WJACOBI) return bytes_like(d, GSCL_F32) * 3 + 256;
+    return (bytes_like(d, GSCL_F32) + 3 * bytes_like(d, s)) * nf + 256;
+}
+
+static int sync_read(gscl_ctx* c, double* host) {
+    GSCL_HIP(hipMemcpyAsync(host, c->result + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GSCL_HIP(hipStreamSynchronize(c->stream));
+    return GSCL_OK;
+}
+
+extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* const* x,
+                          const gscl_grid* const* b, int nf, const gscl_grid* const* coef, int ncoef,
+                          void* workspace, size_t ws_bytes, gscl_solve_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
+    if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "solve outside gscl_begin/gscl_end");
+    if (!sd || !x || !b || !stats) return gscl_fail(GSCL_ERR_ARG, "null argument");
+    if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "solve inside graph capture");
+    const bool poisson = sd->kind == GSCL_K_WJACOBI;
+    const bool vc13 = sd->kind == GSCL_K_VC13_APPLY;
+    if (!poisson && !vc13) return gscl_fail(GSCL_ERR_ARG, "solve kind must be WJACOBI or VC13_APPLY");
+    if (poisson && nf != 1) return gscl_fail(GSCL_ERR_ARG, "Poisson solve takes one field");
+    if (vc13 && nf != 1 && nf != 5) return gscl_fail(GSCL_ERR_UNSUPPORTED, "VC13 solve takes 1 or 5 fields");
+    if (vc13 && (ncoef != 10 || !coef)) return gscl_fail(GSCL_ERR_ARG, "VC13 solve needs 10 coefficient grids");
+    if (sd->check_every < 2 || sd->check_every % 2) return gscl_fail(GSCL_ERR_ARG, "check_every must be even and >= 2");
+    if (sd->precision < GSCL_PREC_F64 || sd->precision > GSCL_PREC_F16_IR)
+        return gscl_fail(GSCL_ERR_ARG, "unknown precision");
+    if (sd->precision != GSCL_PREC_F64 && (sd->inner_sweeps < 2 || sd->inner_sweeps % 2))
+        return gscl_fail(GSCL_ERR_ARG, "inner_sweeps must be even and >= 2");
+    if (poisson && sd->precision != GSCL_PREC_F64 && sd->precision != GSCL_PREC_F32_IR)
+        return gscl_fail(GSCL_ERR_UNSUPPORTED, "Poisson refinement uses F32 correction storage");
+    if (sd->rtol <= 0 || sd->max_sweeps < 1) return gscl_fail(GSCL_ERR_ARG, "rtol and max_sweeps must be positive");
+    for (int f = 0; f < nf; ++f) {
+        if (!grid_ok(x[f]) || !grid_ok(b[f])) return gscl_fail(GSCL_ERR_ARG, "invalid grid");
+        if (x[f]->d.dtype != GSCL_F64 || b[f]->d.dtype != GSCL_F64)
+            return gscl_fail(GSCL_ERR_DTYPE, "solve needs F64 x and b");
+        if (x[f]->d.ndim != 3) return gscl_fail(GSCL_ERR_SHAPE, "solve needs 3D grids");
+        if (x[f]->d.bc != GSCL_BC_DIRICHLET || x[f]->d.bc_value != 0.0)
+            return gscl_fail(GSCL_ERR_ARG, "solve uses a zero Dirichlet boundary");
+    }
+    if (x[0]->d.pitch[0] % 16) return gscl_fail(GSCL_ERR_SHAPE, "solve needs row pitches that are a multiple of 16 elements");
+    const size_t need = gscl_solve_workspace_bytes(sd, x[0], nf);
+    if (!workspace || ws_bytes < need)
+        return gscl_fail(GSCL_ERR_NOMEM, "workspace of %zu bytes needed", need);
+    if (((uintptr_t)workspace) % 256) return gscl_fail(GSCL_ERR_ARG, "workspace must be 256-byte aligned");
+
+    Cleanup cl;
+    cl.ctx = c;
+    // graphs need a capturable stream
+    if (!c->stream) {
+        GSCL_HIP(hipDeviceSynchronize());
+        static thread_local hipStream_t priv[64] = {nullptr};
+        hipStream_t& ps = priv[c->device & 63];
+        if (!ps) GSCL_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+        cl.restore_stream = c->stream;
+        c->stream = ps;
+        cl.swapped = true;
+    }
+    const int R = poisson ? 1 : 2;
+    char* cur = (char*)workspace;
+    const gscl_grid_desc& xd = x[0]->d;
+    int64_t sweeps = 0, outer = 0;
+    double rel = NAN;
+    int rc = GSCL_OK;
+
+    // ||b||^2
+    double bnorm2 = 0.0;
+    for (int f = 0; f < nf; ++f) {
+        gscl_reduce_desc rd{GSCL_R_SUMSQ, 0, 0.0, nullptr};
+        double v = 0.0;
+        if ((rc = gscl_do_reduce(c, &rd, b[f], nullptr, &v))) return rc;
+        bnorm2 += v;
+    }
+    if (!(bnorm2 > 0.0)) {
+        if (bnorm2 != 0.0) return gscl_fail(GSCL_ERR_NUMERIC, "right-hand side norm is %g", bnorm2);
+        for (int f = 0; f < nf; ++f) GSCL_HIP(gk::launch_fill(x[f]->ptr, GSCL_F64, 0.0, geo_of(x[f]), c->stream));
+        GSCL_HIP(hipStreamSynchronize(c->stream));
+        stats->sweeps = 0;
+        stats->outer = 0;
+        stats->rel_residual = 0.0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return GSCL_OK;
+    }
+    // worst-case reduction partials for any launch below, before any capture
+    if ((rc = gscl_reserve(c, xd.n[0] * xd.n[1] * xd.n[2] * 2 + 4096))) return rc;
+    gscl_reduce_desc chk{GSCL_R_SUMSQ, GSCL_RV_RESIDUAL, 0.0, c->result + 8};
+    auto done_check = [&](double res2) -> int {
+        if (res2 != res2) return gscl_fail(GSCL_ERR_NUMERIC, "residual is NaN after %lld sweeps", (long long)sweeps);
+        rel = sqrt(res2 / bnorm2);
+        return rel <= sd->rtol ? 1 : 0;
+    };
+
+    if (sd->precision == GSCL_PREC_F64) {
+        std::vector<gscl_grid*> w(nf);
+        for (int f = 0; f < nf; ++f) w[f] = carve(c, xd, GSCL_F64, R, cur, cl.grids);
+        const int S = sd->check_every;
+        // capture one chunk: x -> w -> x ... (S even ends in x)
+        if ((rc = gscl_graph_begin(c))) return rc;
+        for (int k = 1; k <= S && rc == GSCL_OK; ++k) {
+            const bool odd = k % 2 == 1;
+            std::vector<gscl_grid*> in, out;
+            for (int f = 0; f < nf; ++f) {
+                in.push_back(odd ? x[f] : w[f]);
+                out.push_back(odd ? w[f] : x[f]);
+            }
+            gscl_stencil_desc op;
+            memset(&op, 0, sizeof op);
+            const gscl_reduce_desc* red = k == S ? &chk : nullptr;
+            if (poisson) {
+                op.kind = GSCL_K_WJACOBI;
+                op.p[0] = sd->omega;
+                op.p[1] = sd->h2;
+                in.push_back(const_cast<gscl_grid*>(b[0]));
+                rc = gscl_do_all(c, &op, in.data(), 2, out.data(), 1, red, nullptr);
+            } else {
+                op.kind = GSCL_K_VC13_JACOBI;
+                op.p[0] = sd->kappa;
+                op.p[1] = sd->omega;
+                op.p[2] = nf;
+                for (int f = 0; f < nf; ++f) in.push_back(const_cast<gscl_grid*>(b[f]));
+                for (int k2 = 0; k2 < 10; ++k2) in.push_back(const_cast<gscl_grid*>(coef[k2]));
+                rc = gscl_do_all(c, &op, in.data(), (int)in.size(), out.data(), nf, red, nullptr);
+            }
+        }
+        gscl_graph* gr = nullptr;
+        int rc2 = gscl_graph_end(c, &gr);
+        if (rc) return rc;
+        if (rc2) return rc2;
+        cl.graph = gr;
+        rc = GSCL_ERR_NOCONV;
+        while (sweeps < sd->max_sweeps) {
+            int e = gscl_graph_launch(c, gr);
+            if (e) return e;
+            sweeps += S;
+            double res2 = 0.0;
+            if ((e = sync_read(c, &res2))) return e;
+            int d = done_check(res2);
+            if (d < 0) return d;
+            if (d == 1) {
+                rc = GSCL_OK;
+                break;
+            }
+        }
+    } else {
+        const int s = inner_dtype(sd->precision);
+        const int m = sd->inner_sweeps;
+        std::vector<gscl_grid*> r(nf), rh(nf), d(nf), d2(nf);
+        if (poisson) {
+            r[0] = rh[0] = carve(c, xd, GSCL_F32, 0, cur, cl.grids);
+            d[0] = carve(c, xd, GSCL_F32, 1, cur, cl.grids);
+            d2[0] = carve(c, xd, GSCL_F32, 1, cur, cl.grids);
+        } else {
+            for (int f = 0; f < nf; ++f) {
+                r[f] = carve(c, xd, GSCL_F32, 0, cur, cl.grids);
+                rh[f] = carve(c, xd, s, 0, cur, cl.grids);
+                d[f] = carve(c, xd, s, 2, cur, cl.grids);
+                d2[f] = carve(c, xd, s, 2, cur, cl.grids);
+            }
+            for (int k2 = 0; k2 < 10; ++k2)
+                if (coef[k2]->d.dtype != s)
+                    return gscl_fail(GSCL_ERR_DTYPE, "refinement needs coefficients stored in the inner dtype");
+        }
+        const int64_t npts = xd.n[0] * xd.n[1] * xd.n[2] * nf;
+        rc = GSCL_ERR_NOCONV;
+        while (true) {
+            // outer residual in F64 (stored F32) with its fused norm
+            gscl_stencil_desc op;
+            memset(&op, 0, sizeof op);
+            std::vector<gscl_grid*> in;
+            int e;
+            if (poisson) {
+                op.kind = GSCL_K_POISSON_RESID;
+                op.p[1] = sd->h2;
+                in = {x[0], const_cast<gscl_grid*>(b[0])};
+                e = gscl_do_all(c, &op, in.data(), 2, r.data(), 1, &chk, nullptr);
+            } else {
+                op.kind = GSCL_K_VC13_RESID;
+                op.p[0] = sd->kappa;
+                op.p[2] = nf;
+                for (int f = 0; f < nf; ++f) in.push_back(x[f]);
+                for (int f = 0; f < nf; ++f) in.push_back(const_cast<gscl_grid*>(b[f]));
+                for (int k2 = 0; k2 < 10; ++k2) in.push_back(const_cast<gscl_grid*>(coef[k2]));
+                e = gscl_do_all(c, &op, in.data(), (int)in.size(), r.data(), nf, &chk, nullptr);
+            }
+            if (e) return e;
+            double res2 = 0.0;
+            if ((e = sync_read(c, &res2))) return e;
+            int dn = done_check(res2);
+            if (dn < 0) return dn;
+            if (dn == 1) {
+                rc = GSCL_OK;
+                break;
+            }
+            if (sweeps >= sd->max_sweeps) break;
+            ++outer;
+            // scale into the inner storage range (F16 needs it; others use 1)
+            const double sigma = s == GSCL_F16 ? sqrt(res2 / (double)npts) : 1.0;
+            for (int f = 0; f < nf; ++f) {
+                const gk::Geo g = geo_of(x[f]);
+                if (!poisson) GSCL_HIP(gk::launch_axpby(rh[f]->ptr, s, r[f]->ptr, GSCL_F32, 1.0 / sigma, nullptr, 0, 0.0, g, c->stream));
+                GSCL_HIP(gk::launch_fill(d[f]->ptr, s == GSCL_F64 ? GSCL_F64 : (poisson ? GSCL_F32 : s), 0.0, g, c->stream));
+            }
+            for (int k = 1; k <= m; ++k) {
+                const bool odd = k % 2 == 1;
+                std::vector<gscl_grid*> iin, iout;
+                gscl_stencil_desc iop;
+                memset(&iop, 0, sizeof iop);
+                if (poisson) {
+                    iop.kind = GSCL_K_WJACOBI;
+                    iop.p[0] = sd->omega;
+                    iop.p[1] = sd->h2;
+                    iin = {odd ? d[0] : d2[0], rh[0]};
+                    iout = {odd ? d2[0] : d[0]};
+                    e = gscl_do_all(c, &iop, iin.data(), 2, iout.data(), 1, nullptr, nullptr);
+                } else {
+                    iop.kind = GSCL_K_VC13_JACOBI;
+                    iop.p[0] = sd->kappa;
+                    iop.p[1] = sd->omega;
+                    iop.p[2] = nf;
+                    for (int f = 0; f < nf; ++f) iin.push_back(odd ? d[f] : d2[f]);
+                    for (int f = 0; f < nf; ++f) iin.push_back(rh[f]);
+                    for (int k2 = 0; k2 < 10; ++k2) iin.push_back(const_cast<gscl_grid*>(coef[k2]));
+                    for (int f = 0; f < nf; ++f) iout.push_back(odd ? d2[f] : d[f]);
+                    e = gscl_do_all(c, &iop, iin.data(), (int)iin.size(), iout.data(), nf, nullptr, nullptr);
+                }
+                if (e) return e;
+            }
+            sweeps += m;
+            for (int f = 0; f < nf; ++f)
+                GSCL_HIP(gk::launch_axpby(x[f]->ptr, GSCL_F64, x[f]->ptr, GSCL_F64, 1.0, d[f]->ptr,
+                                          poisson ? GSCL_F32 : s, sigma, geo_of(x[f]), c->stream));
+        }
+    }
+    GSCL_HIP(hipStreamSynchronize(c->stream));
+    stats->sweeps = sweeps;
+    stats->outer = outer;
+    stats->rel_residual = rel;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc == GSCL_ERR_NOCONV)
+        return gscl_fail(GSCL_ERR_NOCONV, "no convergence after %lld sweeps (relative residual %g)",
+                         (long long)sweeps, rel);
+    return rc;
+}

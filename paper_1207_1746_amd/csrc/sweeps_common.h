@@ -16,10 +16,13 @@ static hipError_t run(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* 
     const int n = a.ntx * a.nty * a.ncz;
     *nblocks = n;
     if (n == 0) return hipSuccess;
-    if (red)
+    if (red) {
         hipLaunchKernelGGL((tiled_sweep<Op, V, NW, true>), dim3(n), dim3(64 * NW), 0, s, a);
-    else
-        hipLaunchKernelGGL((tiled_sweep<Op, V, NW, false>), dim3(n), dim3(64 * NW), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_reduce_finish(a.ra, n, s);
+    }
+    hipLaunchKernelGGL((tiled_sweep<Op, V, NW, false>), dim3(n), dim3(64 * NW), 0, s, a);
     return hipGetLastError();
 }
 

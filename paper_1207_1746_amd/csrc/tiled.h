@@ -14,7 +14,8 @@
 //   * halo values outside the domain are synthesized from the boundary rule
 //     (no stored halo, no halo-fill pass).
 //   * an optional fused reduction of a per-point value (Section 5.2 fuse) is
-//     accumulated in FP64 registers and finished by the last block.
+//     accumulated in FP64 registers; block partials are folded by a finish
+//     kernel.
 #pragma once
 
 #include "kcommon.h"
@@ -70,8 +71,12 @@ __device__ __forceinline__ void load_pw(const S* base, const Geo& g, int gx, int
     }
 }
 
+// One tile of the sweep: tile index -> (x tile, y tile, z chunk), march the
+// chunk, write the outputs, and add the fused-reduction operand of every
+// interior point of the tile to `acc`.  Every thread of the block must call it
+// with the same tile (it synchronizes the block).
 template <class Op, int V, int NW, bool RED>
-__global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
+__device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, double& acc) {
     using T = typename Op::T;
     using SN = typename Op::SN;
     using SA = typename Op::SA;
@@ -91,8 +96,6 @@ __global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
 
     const Geo& g = a.g;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int ntiles = a.ntx * a.nty * a.ncz;
-    const int tile = xcd_remap(blockIdx.x, ntiles);
     const int xt = tile % a.ntx;
     const int rest = tile / a.ntx;
     const int yt = rest % a.nty;
@@ -143,7 +146,6 @@ __global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
     load_halo(z0, xh, yh);
     load_point(z0, pa, pb);
 
-    double acc = 0.0;
     const bool row_ok = gy < g.ny;
 
     for (int z = z0; z < z1; ++z) {
@@ -269,7 +271,15 @@ __global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
                 for (int v = 0; v < V; ++v) pb[i][v] = pbn[i][v];
         }
     }
-    if (RED) block_reduce_finish(acc, a.ra, tile, ntiles);
+}
+
+template <class Op, int V, int NW, bool RED>
+__global__ __launch_bounds__(64 * NW) void tiled_sweep(TArgs a) {
+    const int ntiles = a.ntx * a.nty * a.ncz;
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    double acc = 0.0;
+    sweep_tile<Op, V, NW, RED>(a, tile, acc);
+    if (RED) block_reduce(acc, a.ra, tile);
 }
 
 }  // namespace gk

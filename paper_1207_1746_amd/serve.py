@@ -1,0 +1,149 @@
+"""Continuous-batching Poisson solve server on top of the batched executor.
+
+Requests (cube sides N, right-hand sides f) arrive over time.  A FIFO queue
+holds arrivals; a request is admitted into the batch as soon as a slot is
+free and its HBM footprint fits the budget, so requests that arrive while
+others are on the GPU join the running set at the next step and their sweeps
+overlap on the device.  After every step the server polls the per-slot
+states, retires finished requests (latency = completion - arrival), frees
+their memory and admits more.
+
+All stencil work runs in the library's kernels (gscl_batch_*); this module only
+moves requests between queue, slots and results.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import paper_1207_1746_amd as G
+
+
+@dataclass
+class Job:
+    rid: int
+    n: int
+    h2: float
+    arrival: float
+    f: object                 # device F64 tensor (N, N, N) or Grid
+    u: object = None          # Grid holding the answer
+    fg: object = None
+    slot: int | None = None
+    admitted_at: float | None = None
+    done_at: float | None = None
+    sweeps: int = 0
+    rel_residual: float = float("nan")
+    state: int = 0
+
+
+@dataclass
+class ServeReport:
+    jobs: list
+    wall: float
+    steps: int
+    max_running: int
+    occupancy: list = field(default_factory=list)
+
+    def latencies(self):
+        return sorted(j.done_at - j.arrival for j in self.jobs if j.done_at is not None)
+
+    def summary(self) -> dict:
+        lat = self.latencies()
+
+        def pct(p):
+            if not lat:
+                return float("nan")
+            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+            return lat[k]
+
+        done = [j for j in self.jobs if j.state == 2]
+        return {"requests": len(self.jobs), "converged": len(done),
+                "solves_per_s": len(done) / self.wall if self.wall > 0 else float("nan"),
+                "p50_s": pct(50), "p99_s": pct(99), "wall_s": self.wall, "steps": self.steps,
+                "max_running": self.max_running,
+                "mean_occupancy": sum(self.occupancy) / len(self.occupancy) if self.occupancy else 0.0}
+
+
+class SolveServer:
+    def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
+                 rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
+                 hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7):
+        self.ctx = ctx
+        self.batch = G.Batch(ctx, max_slots=max_slots, precision=precision,
+                             sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,
+                             rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps)
+
+    def _admit(self, job: Job, now: float) -> bool:
+        shape = (job.n, job.n, job.n)
+        if job.u is None:
+            job.u = self.ctx.grid(shape, G.F64, halo=1)
+            job.u.fill(0.0)
+            job.fg = job.f if isinstance(job.f, G.Grid) else self.ctx.grid(shape, G.F64, halo=0, data=job.f)
+        slot = self.batch.admit(job.u, job.fg, job.h2)
+        if slot is None:
+            return False
+        job.slot = slot
+        job.admitted_at = now
+        return True
+
+    def run(self, jobs: list[Job], realtime: bool = True) -> ServeReport:
+        """Serve `jobs` (sorted by arrival).  realtime=False admits by arrival
+        order only (closed loop, no waiting for the clock)."""
+        pending = sorted(jobs, key=lambda j: j.arrival)
+        queue: list[Job] = []
+        running: dict[int, Job] = {}
+        t0 = time.perf_counter()
+        steps = 0
+        max_running = 0
+        occ = []
+        i = 0
+        while i < len(pending) or queue or running:
+            now = time.perf_counter() - t0
+            while i < len(pending) and (not realtime or pending[i].arrival <= now):
+                queue.append(pending[i])
+                i += 1
+            while queue:
+                if not self._admit(queue[0], now):
+                    break
+                job = queue.pop(0)
+                running[job.slot] = job
+            max_running = max(max_running, len(running))
+            if not running:
+                # idle until the next arrival
+                if i < len(pending):
+                    time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))
+                continue
+            occ.append(len(running))
+            self.batch.step()
+            steps += 1
+            for slot in self.batch.poll():
+                job = running.pop(slot)
+                st = self.batch.retire(slot)
+                job.done_at = time.perf_counter() - t0
+                job.sweeps, job.rel_residual, job.state = st["sweeps"], st["rel_residual"], st["state"]
+        return ServeReport(jobs, time.perf_counter() - t0, steps, max_running, occ)
+
+    def close(self):
+        self.batch.close()
+
+
+def serve_sequential(ctx: G.Context, jobs: list[Job], rtol: float = 1e-8, omega: float = 6 / 7,
+                     check_every: int = 64, precision: int = G.PREC_F64, inner_sweeps: int = 64,
+                     realtime: bool = True) -> ServeReport:
+    """One solve at a time with gscl_solve (the plain path), same queueing rules."""
+    t0 = time.perf_counter()
+    for job in sorted(jobs, key=lambda j: j.arrival):
+        now = time.perf_counter() - t0
+        if realtime and job.arrival > now:
+            time.sleep(job.arrival - now)
+        shape = (job.n, job.n, job.n)
+        job.u = ctx.grid(shape, G.F64, halo=1)
+        job.u.fill(0.0)
+        job.fg = job.f if isinstance(job.f, G.Grid) else ctx.grid(shape, G.F64, halo=0, data=job.f)
+        job.admitted_at = time.perf_counter() - t0
+        st = ctx.solve(G.K_WJACOBI, [job.u], [job.fg], omega=omega, h2=job.h2, rtol=rtol,
+                       check_every=check_every, precision=precision, inner_sweeps=inner_sweeps)
+        job.done_at = time.perf_counter() - t0
+        job.sweeps, job.rel_residual, job.state = st["sweeps"], st["rel_residual"], 2
+    return ServeReport(jobs, time.perf_counter() - t0, 0, 1, [1])

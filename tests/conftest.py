@@ -31,3 +31,18 @@ def pytest_runtest_setup(item):
     if item.get_closest_marker("gpu") is not None:
         sys.stdout.write(f"\n[gpu-case] {item.nodeid}\n")
         sys.stdout.flush()
+
+
+@pytest.fixture
+def sctx():
+    """A library context on a side stream (graph capture needs a non-null
+    stream); torch's current stream is the same stream inside the test."""
+    import torch
+    import paper_1207_1746_amd as G
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c = G.Context(0, stream=s)
+        yield c
+        c.end()
+        c.finalize()

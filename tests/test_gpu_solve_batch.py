@@ -1,0 +1,210 @@
+"""GPU parity for the solver, the batched executor and the serving loop.
+
+* gscl_solve F64 (Section 5.2: sweep + fused check until done) takes exactly
+  the oracle's number of sweeps (the check is fused into the last sweep of
+  each chunk on both sides) and returns the same iterate to 1e-11 relative.
+* Mixed-precision refinement: the oracle recomputes the FP64 residual of the
+  GPU's answer; it must meet rtol (1e-10), and the answer must agree with the
+  oracle's tight FP64 solution within cond(A) * rtol.
+* Batched executor: every request's answer is bit-identical alone and in a
+  mix (per-slot arithmetic and reduction order do not depend on the mix), and
+  matches the one-at-a-time solver.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1207_1746_amd as G
+from paper_1207_1746_amd import serve as SV
+from paper_1207_1746_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _req(n, seed=0, rid=0):
+    r = W.poisson_requests(count=1, qps=float("inf"), nmin=n, nmax=n, seed_index=seed)[0]
+    r.rid = rid
+    return r
+
+
+def _oracle_rel_residual(u, f, h2):
+    _, _, res = oracle.wjacobi_sweep(u, f, 6 / 7, h2)
+    return math.sqrt(oracle.sumsq(res) / oracle.sumsq(f))
+
+
+@pytest.mark.parametrize("n,S", [(20, 32), (33, 16)])
+def test_poisson_f64_matches_oracle(ctx, n, S):
+    req = _req(n, seed=n)
+    ustar, f = W.poisson_fields(req)
+    u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+    st = ctx.solve(G.K_WJACOBI, [u], [gf], h2=req.h2, rtol=1e-8, check_every=S)
+    uo, so, relo, conv = oracle.poisson_solve(f, req.h2, 6 / 7, 1e-8, S, 10 ** 6)
+    assert conv and st["sweeps"] == so
+    assert abs(st["rel_residual"] - relo) <= 1e-6 * relo  # cancellation at 1e-8
+    got = u.numpy()
+    assert np.abs(got - uo).max() <= 1e-11 * np.abs(uo).max()
+    # manufactured solution: ||u - u*||_2 <= ||r||_2 / |lambda_min|
+    lam_min = abs(W.mode_eigenvalue(n, 1, 1, 1))
+    r_now = _oracle_rel_residual(got, f, req.h2) * math.sqrt(oracle.sumsq(f))
+    assert math.sqrt(oracle.sumsq(got - ustar)) <= r_now / lam_min * 1.0001
+
+
+def test_poisson_f32_refinement_reaches_1e10(sctx):
+    ctx = sctx
+    n = 28
+    req = _req(n, seed=3)
+    ustar, f = W.poisson_fields(req)
+    u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+    st = ctx.solve(G.K_WJACOBI, [u], [gf], h2=req.h2, rtol=1e-10, check_every=2,
+                   precision=G.PREC_F32_IR, inner_sweeps=128)
+    got = u.numpy()
+    rel = _oracle_rel_residual(got, f, req.h2)
+    assert rel <= 1e-10 * 1.001 and st["outer"] >= 1
+    assert abs(rel - st["rel_residual"]) <= 1e-4 * rel  # cancellation at 1e-10
+    # matches the FP64 solve to the accuracy rtol allows
+    uo, _, _, _ = oracle.poisson_solve(f, req.h2, 6 / 7, 1e-12, 32, 10 ** 6)
+    lam_min = abs(W.mode_eigenvalue(n, 1, 1, 1))
+    lam_max = abs(W.mode_eigenvalue(n, n, n, n))
+    assert np.abs(got - uo).max() <= 2e-10 * lam_max / lam_min * np.abs(uo).max()
+
+
+def test_poisson_solver_errors(ctx):
+    req = _req(12)
+    _, f = W.poisson_fields(req)
+    u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+    with pytest.raises(G.GsclError) as e:
+        ctx.solve(G.K_WJACOBI, [u], [gf], h2=req.h2, rtol=1e-12, check_every=4, max_sweeps=8)
+    assert e.value.code == G.ERR_NOCONV
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    gb = ctx.grid(f.shape, G.F64, halo=0, data=bad)
+    u.fill(0.0)
+    with pytest.raises(G.GsclError) as e:
+        ctx.solve(G.K_WJACOBI, [u], [gb], h2=req.h2, rtol=1e-8, check_every=4)
+    assert e.value.code == G.ERR_NUMERIC
+    z = ctx.grid(f.shape, G.F64, halo=0).fill(0.0)
+    u.fill(1.0)
+    st = ctx.solve(G.K_WJACOBI, [u], [z], h2=req.h2, rtol=1e-8, check_every=4)
+    assert st["sweeps"] == 0 and np.all(u.numpy() == 0.0)
+
+
+@pytest.mark.parametrize("prec,dt", [(G.PREC_F64, G.BF16), (G.PREC_F32_IR, G.F32),
+                                     (G.PREC_BF16_IR, G.BF16), (G.PREC_F16_IR, G.F16)])
+def test_vc13_solve_per_precision(ctx, prec, dt):
+    shape = (10, 12, 20)
+    nf = 5
+    c, b = W.vc13_grids(shape[2], shape[1], shape[0], nf)
+    gx = [ctx.grid(shape, G.F64, halo=2).fill(0.0) for _ in range(nf)]
+    gb = [ctx.grid(shape, G.F64, halo=0, data=x) for x in b]
+    gc = [ctx.grid(shape, dt, halo=0, data=x) for x in c]
+    st = ctx.solve(G.K_VC13_APPLY, gx, gb, gc, kappa=W.VC13_KAPPA, rtol=1e-10, check_every=8,
+                   precision=prec, inner_sweeps=16)
+    bn = math.sqrt(sum(oracle.sumsq(x) for x in b))
+    rn = math.sqrt(sum(oracle.sumsq(oracle.vc13_residual(gx[f].numpy(), b[f], c, W.VC13_KAPPA))
+                       for f in range(nf)))
+    assert rn / bn <= 1e-10 * 1.001, (prec, rn / bn, st)
+    for f in range(nf):
+        xo, _, _ = oracle.vc13_jacobi_solve(b[f], c, W.VC13_KAPPA, 6 / 7, 1e-14, 10000)
+        # A is diagonally dominant with cond(A) < 10 for these coefficients
+        assert np.abs(gx[f].numpy() - xo).max() <= 1e-9 * 10 * np.abs(xo).max()
+
+
+def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8):
+    """Run requests through one batch; admit_at[i] = step index to admit request i."""
+    b = G.Batch(ctx, max_slots=8, precision=prec, sweeps_per_step=S, use_graph=use_graph, rtol=rtol,
+                hbm_budget=1 << 30)
+    admit_at = admit_at or [0] * len(reqs)
+    grids = {}
+    out = {}
+    slots = {}
+    step = 0
+    while len(out) < len(reqs):
+        for i, r in enumerate(reqs):
+            if admit_at[i] == step and i not in slots:
+                _, f = W.poisson_fields(r)
+                u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+                gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+                grids[i] = (u, gf)
+                s = b.admit(u, gf, r.h2)
+                assert s is not None
+                slots[i] = s
+        b.step()
+        step += 1
+        for s in b.poll():
+            i = [k for k, v in slots.items() if v == s and k not in out][0]
+            st = b.retire(s)
+            out[i] = (grids[i][0].numpy(), st)
+        assert step < 100000
+    b.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [G.PREC_F64, G.PREC_F32_IR])
+def test_batch_alone_equals_mix(ctx, prec):
+    reqs = [_req(n, seed=n, rid=i) for i, n in enumerate((24, 37, 17, 45))]
+    S = 16
+    mix = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 3, 5])
+    for i, r in enumerate(reqs):
+        alone = _batch_solve(ctx, [r], prec, S)[0]
+        assert np.array_equal(alone[0], mix[i][0]), i
+        assert alone[1]["sweeps"] == mix[i][1]["sweeps"] and alone[1]["state"] == 2
+        _, f = W.poisson_fields(r)
+        assert _oracle_rel_residual(mix[i][0], f, r.h2) <= 1e-8 * 1.01
+
+
+def test_batch_f64_matches_solver_and_oracle(sctx):
+    ctx = sctx
+    reqs = [_req(n, seed=n + 1, rid=i) for i, n in enumerate((19, 30))]
+    S = 16
+    res = _batch_solve(ctx, reqs, G.PREC_F64, S, use_graph=False)
+    resg = _batch_solve(ctx, reqs, G.PREC_F64, S, use_graph=True)
+    for i, r in enumerate(reqs):
+        _, f = W.poisson_fields(r)
+        uo, so, _, _ = oracle.poisson_solve(f, r.h2, 6 / 7, 1e-8, S, 10 ** 6)
+        assert res[i][1]["sweeps"] == so
+        assert np.abs(res[i][0] - uo).max() <= 1e-11 * np.abs(uo).max()
+        assert np.array_equal(res[i][0], resg[i][0])
+        u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+        gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+        st = ctx.solve(G.K_WJACOBI, [u], [gf], h2=r.h2, rtol=1e-8, check_every=S)
+        assert st["sweeps"] == so and np.array_equal(u.numpy(), res[i][0])
+
+
+def test_batch_budget_admission(ctx):
+    r = _req(40)
+    _, f = W.poisson_fields(r)
+    b = G.Batch(ctx, max_slots=4, precision=G.PREC_F64, sweeps_per_step=8, hbm_budget=2 * 40 ** 3 * 8 * 3)
+    fp = b.footprint((40, 40, 40))
+    assert fp >= 3 * 40 ** 3 * 8
+    grids = [(ctx.grid(f.shape, G.F64, halo=1).fill(0.0), ctx.grid(f.shape, G.F64, halo=0, data=f))
+             for _ in range(3)]
+    assert b.admit(*grids[0], r.h2) is not None
+    assert b.admit(*grids[1], r.h2) is not None
+    assert b.admit(*grids[2], r.h2) is None  # over budget: caller queues
+    b.close()
+
+
+def test_serving_loop_continuous_batching(sctx):
+    ctx = sctx
+    reqs = W.poisson_requests(count=12, qps=200.0, nmin=16, nmax=40, seed_index=7)
+    jobs = []
+    for r in reqs:
+        _, f = W.poisson_fields(r)
+        jobs.append(SV.Job(r.rid, r.n, r.h2, r.arrival, f))
+    srv = SV.SolveServer(ctx, precision=G.PREC_F32_IR, sweeps_per_step=32, rtol=1e-8, max_slots=8)
+    rep = srv.run(jobs)
+    srv.close()
+    s = rep.summary()
+    assert s["converged"] == len(jobs) and s["p99_s"] >= s["p50_s"] > 0
+    assert rep.max_running > 1  # requests overlapped on the device
+    for j, r in zip(jobs, reqs):
+        _, f = W.poisson_fields(r)
+        got = j.u.numpy()
+        assert _oracle_rel_residual(got, f, r.h2) <= 1e-8 * 1.01
+        alone = _batch_solve(ctx, [r], G.PREC_F32_IR, 32)[0]
+        assert np.array_equal(alone[0], got)
