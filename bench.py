@@ -44,19 +44,23 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str, per_launch_bytes_alg: float):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+def measured_traffic(workload_key: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (profiles/<key>_traffic.md), if the counters were
     taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{workload_key}_traffic.md")
     if not os.path.exists(path):
         return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip("- *`").strip()] = v.strip().strip("`")
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
     try:
-        data = json.load(open(path))
-        rec = data.get(workload_key)
-        if not rec or rec.get("kernel_hash") != kernel_hash():
-            return None
         return float(rec["bytes_per_launch"])
-    except Exception:
+    except (KeyError, ValueError):
         return None
 
 
@@ -233,7 +237,52 @@ class Image:
                 "sample": f"{reps} single planes in {dt:.1f} s"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image}
+class Serve:
+    """Stream of Poisson solve requests: batched mixed-precision serving
+    (continuous batching, F32 correction sweeps, F64 residual) against the
+    one-solve-at-a-time F64 solver, both to the same relative residual."""
+    key = "serve"
+    bytes_per_point = 12  # F32 correction sweep: read d, rhs; write d'
+
+    def __init__(self, ctx, count=48, nmin=32, nmax=64, qps=200.0, rtol=1e-10):
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import serve as SV
+        from paper_1207_1746_amd import workloads as W
+        self.G, self.SV, self.W = G, SV, W
+        self.ctx = ctx
+        self.reqs = W.poisson_requests(count=count, qps=qps, nmin=nmin, nmax=nmax, seed_index=1)
+        self.fields = {r.rid: W.poisson_fields(r)[1] for r in self.reqs}
+        self.rtol = rtol
+        self.count, self.nmin, self.nmax, self.qps = count, nmin, nmax, qps
+        self.unit = "solves/s"
+        self.points = 1
+        self.units_per_step = count
+        self.last = {}
+
+    def _jobs(self):
+        return [self.SV.Job(r.rid, r.n, r.h2, r.arrival,
+                            self.ctx.grid((r.n,) * 3, self.G.F64, halo=0, data=self.fields[r.rid]))
+                for r in self.reqs]
+
+    def step(self, ev=None):
+        srv = self.SV.SolveServer(self.ctx, precision=self.G.PREC_F32_IR, sweeps_per_step=64,
+                                  rtol=self.rtol, max_slots=64)
+        rep = srv.run(self._jobs())
+        srv.close()
+        self.last["batched"] = rep.summary()
+
+    def sequential(self):
+        rep = self.SV.serve_sequential(self.ctx, self._jobs(), rtol=self.rtol, check_every=64)
+        return rep.summary()
+
+    def config(self):
+        return {"workload": f"{self.count} Poisson solve requests, cube sides log-uniform in "
+                            f"[{self.nmin},{self.nmax}], 3 sine modes, Poisson arrivals at {self.qps}/s, "
+                            f"weighted Jacobi omega=6/7 to relative residual {self.rtol}",
+                "serving": "continuous batching, F32 correction sweeps + F64 residual (refinement)"}
+
+
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image, "serve": Serve}
 
 
 class KernelEvents:
@@ -262,6 +311,26 @@ class KernelEvents:
         return sum(ts) / len(ts) if ts else float("nan"), len(ts)
 
 
+def serve_main(args, ctx, wl):
+    wl.step()  # warm-up: builds the graph, pages in kernels
+    t0 = time.perf_counter()
+    wl.step()
+    sec = time.perf_counter() - t0
+    bat = wl.last["batched"]
+    seq = wl.sequential()
+    out = {"metric": METRIC, "value": round(bat["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(sec * 1e3, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (seeded)",
+           "config": wl.config(),
+           "latency_p50_s": round(bat["p50_s"], 4), "latency_p99_s": round(bat["p99_s"], 4),
+           "batched": bat, "sequential_f64": seq,
+           "speedup_vs_sequential_f64": round(bat["solves_per_s"] / seq["solves_per_s"], 3),
+           "roofline": None, "cpu_baseline": None}
+    ctx.end()
+    ctx.finalize()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,7 +341,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile", default=None, help="V,NW,cz override for the dominant kernel")
+    ap.add_argument("--print-kernel-hash", action="store_true")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_hash())
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -288,6 +361,8 @@ def main():
         if kind is not None:
             ctx.tile_set(kind, wl.gu if args.config == "varcoef" else wl.a, (V, NW, cz))
     stream = ctx.stream
+    if args.config == "serve":
+        return serve_main(args, ctx, wl)
 
     for _ in range(args.warmup):
         wl.step()
@@ -304,7 +379,7 @@ def main():
     kmean_ms, nk = ev.mean_ms()
     per_launch_bytes = wl.bytes_per_point * wl.points
     achieved = per_launch_bytes / (kmean_ms * 1e-3) / 1e9
-    traffic = measured_traffic(wl.key, per_launch_bytes)
+    traffic = measured_traffic(wl.key)
 
     if args.copy_calibration:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

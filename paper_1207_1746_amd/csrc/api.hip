@@ -209,22 +209,43 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
     if (it != c->tiles.end()) return it->second;
     gk::TileCfg t;
     const int64_t nx = d.n[0];
+    if (kind == GSCL_K_IMG_BOX5_LAP) {  // rows per block of the image kernel (measured best: 8)
+        t.V = 4;
+        t.NW = 4;
+        t.cz = 8;
+        return t;
+    }
     const bool r2 = kind == GSCL_K_VC13_APPLY || kind == GSCL_K_VC13_JACOBI || kind == GSCL_K_VC13_RESID;
-    const bool wide = dtype != GSCL_F64 && !r2;
-    if (wide)
-        t.V = nx >= 256 ? 4 : (nx >= 128 ? 2 : 1);
-    else
+    // Defaults from tile sweeps on MI355X: 16-byte lanes (V = 4 for F32, V = 2
+    // for F64), 4 waves per block, and short z chunks so that a launch has
+    // several thousand blocks (about 8-16 per CU); radius-2 multi-field
+    // kernels use one element per lane to keep their register queues small.
+    if (r2)
         t.V = nx >= 128 ? 2 : 1;
-    t.NW = r2 ? 4 : 8;
-    if (d.n[1] <= 4) t.NW = 4;
+    else if (dtype == GSCL_F64)
+        t.V = nx >= 128 ? 2 : 1;
+    else
+        t.V = nx >= 256 ? 4 : (nx >= 128 ? 2 : 1);
+    if (r2 && t.V == 2 && d.n[2] > 1) t.V = 1;
+    t.NW = 4;
     const int64_t ntx = (nx + 64 * t.V - 1) / (64 * t.V);
     const int64_t nty = (d.n[1] + t.NW - 1) / t.NW;
     const int64_t cols = ntx * nty;
-    // aim for ~2048 blocks, at least 4 planes per block for 3D (halo planes)
-    int64_t cz = (cols * d.n[2]) / 2048;
-    const int64_t czmin = d.ndim == 3 ? 4 : 1;
+    // aim for ~8192 blocks (4096 for F64), at least 2 planes per block in 3D
+    const int64_t want = dtype == GSCL_F64 ? 4096 : 8192;
+    int64_t cz = (cols * d.n[2]) / want;
+    const int64_t czmin = d.ndim == 3 ? 2 : 1;
     cz = std::max(czmin, std::min<int64_t>(cz, 64));
     t.cz = (int)std::max<int64_t>(1, std::min<int64_t>(cz, std::max<int64_t>(d.n[2], 1)));
+    return t;
+}
+
+// Fused reductions pay per block (partials and the finish fold): keep their
+// launches to about 512 blocks by lengthening the z chunk (measured best).
+static gk::TileCfg reduce_tile(gk::TileCfg t, const gscl_grid_desc& d) {
+    const int64_t ntx = (d.n[0] + 64 * t.V - 1) / (64 * t.V);
+    const int64_t nty = (d.n[1] + t.NW - 1) / t.NW;
+    while ((int64_t)t.cz < d.n[2] && ntx * nty * ((d.n[2] + t.cz - 1) / t.cz) > 512) t.cz *= 2;
     return t;
 }
 
@@ -444,6 +465,7 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             a.operand = red ? fused->operand : 0;
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             if (red) {
+                t = reduce_tile(t, g0->d);
                 if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
                 fill_red(c, fused, a.ra);
             }
@@ -464,6 +486,7 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             a.operand = red ? fused->operand : 0;
             gk::TileCfg t = pick_tile(c, GSCL_K_WJACOBI, GSCL_F64, g0->d);
             if (red) {
+                t = reduce_tile(t, g0->d);
                 if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
                 fill_red(c, fused, a.ra);
             }
@@ -484,6 +507,7 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             a.operand = red ? fused->operand : 0;
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             if (red) {
+                t = reduce_tile(t, g0->d);
                 if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
                 fill_red(c, fused, a.ra);
             }
@@ -500,8 +524,9 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             const int lk = (int)op->p[0];
             if (lk != 4 && lk != 8) return gscl_fail(GSCL_ERR_ARG, "Laplacian kind p[0] must be 4 or 8");
             if (red) return gscl_fail(GSCL_ERR_UNSUPPORTED, "IMG_BOX5_LAP has no fused reduction");
+            gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             he = gk::launch_image((const uint8_t*)g0->ptr, (uint8_t*)out[0]->ptr, (int16_t*)out[1]->ptr, geo_of(g0),
-                                  lk, c->stream);
+                                  lk, t.cz, c->stream);
             break;
         }
         case GSCL_K_VC13_APPLY:
@@ -531,6 +556,7 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             a.operand = red ? fused->operand : 0;
             gk::TileCfg t = pick_tile(c, op->kind, dnb, g0->d);
             if (red) {
+                t = reduce_tile(t, g0->d);
                 if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
                 fill_red(c, fused, a.ra);
             }

@@ -50,14 +50,13 @@ __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, va - vb);
 }
 
-template <int CY>
 __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ img,
                                                   uint8_t* __restrict__ box,
-                                                  int16_t* __restrict__ lap, Geo g) {
+                                                  int16_t* __restrict__ lap, Geo g, int cy) {
     const int x = (blockIdx.x * 256 + threadIdx.x) * 16;
     if (x >= g.nx) return;
-    const int y0 = blockIdx.y * CY;
-    const int y1 = min(y0 + CY, g.ny);
+    const int y0 = blockIdx.y * cy;
+    const int y1 = min(y0 + cy, g.ny);
     const int z = blockIdx.z;
 
     Row6 q[5];
@@ -92,7 +91,11 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
                     (box1(ho >> 16) << 24);
         }
         const int64_t off = (int64_t)z * g.pz + (int64_t)y * g.py + x;
-        *reinterpret_cast<uint4*>(box + off) = make_uint4(bo[0], bo[1], bo[2], bo[3]);
+        {
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 vb = {bo[0], bo[1], bo[2], bo[3]};
+            __builtin_nontemporal_store(vb, reinterpret_cast<u32x4*>(box + off));
+        }
 
         // Laplacian from rows y-1 (q[1]), y (q[2]), y+1 (q[3]); bias 1024 per half
         uint32_t lo[8];
@@ -110,9 +113,13 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
             lo[2 * k] = pk_sub16(__builtin_amdgcn_perm(lq, le, 0x05040100u), 0x04000400u);
             lo[2 * k + 1] = pk_sub16(__builtin_amdgcn_perm(lq, le, 0x07060302u), 0x04000400u);
         }
-        uint4* lp = reinterpret_cast<uint4*>(lap + off);
-        lp[0] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-        lp[1] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
+        {
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            u32x4* lp = reinterpret_cast<u32x4*>(lap + off);
+            u32x4 l0 = {lo[0], lo[1], lo[2], lo[3]}, l1 = {lo[4], lo[5], lo[6], lo[7]};
+            __builtin_nontemporal_store(l0, lp);
+            __builtin_nontemporal_store(l1, lp + 1);
+        }
 
         if (more) {
 #pragma unroll
@@ -159,12 +166,12 @@ __global__ __launch_bounds__(256) void image_generic(const uint8_t* __restrict__
 }
 
 hipError_t launch_image(const uint8_t* img, uint8_t* box, int16_t* lap, const Geo& g,
-                        int lap_kind, hipStream_t s) {
+                        int lap_kind, int cy, hipStream_t s) {
     if (g.nx == 0 || g.ny == 0 || g.nz == 0) return hipSuccess;
+    if (cy < 1) cy = 32;
     if (lap_kind == 4 && g.nx % 16 == 0) {
-        constexpr int CY = 64;
-        dim3 grid((g.nx / 16 + 255) / 256, (g.ny + CY - 1) / CY, g.nz);
-        hipLaunchKernelGGL((image_fast<CY>), grid, dim3(256), 0, s, img, box, lap, g);
+        dim3 grid((g.nx / 16 + 255) / 256, (g.ny + cy - 1) / cy, g.nz);
+        hipLaunchKernelGGL(image_fast, grid, dim3(256), 0, s, img, box, lap, g, cy);
     } else {
         dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
         hipLaunchKernelGGL(image_generic, grid, dim3(256), 0, s, img, box, lap, g, lap_kind);

@@ -19,9 +19,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const S* __restrict__ a,
         const int64_t base = (int64_t)z * g.pz + (int64_t)y * g.py;
         for (int x = lane * V; x < g.nx; x += 64 * V) {
             if (x + V <= g.nx) {
-                Vec<S, V> va = vload<S, V>(a + base + x);
+                Vec<S, V> va = vload_nt<S, V>(a + base + x);
                 Vec<S, V> vb;
-                if (DIFF) vb = vload<S, V>(b + base + x);
+                if (DIFF) vb = vload_nt<S, V>(b + base + x);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     double v = from_s<double>(va.v[i]);

@@ -52,6 +52,65 @@ __device__ __forceinline__ void vstore(S* p, const Vec<S, V>& x) {
     *reinterpret_cast<Vec<S, V>*>(p) = x;
 }
 
+// Non-temporal (streaming) variants for data touched once per sweep: they
+// keep single-use streams from evicting reused lines from the caches.
+template <int B> struct RawT;
+template <> struct RawT<1> { typedef unsigned char t; };
+template <> struct RawT<2> { typedef unsigned short t; };
+template <> struct RawT<4> { typedef unsigned int t; };
+template <> struct RawT<8> { typedef unsigned int t __attribute__((ext_vector_type(2))); };
+template <> struct RawT<16> { typedef unsigned int t __attribute__((ext_vector_type(4))); };
+
+template <class S, int V>
+__device__ __forceinline__ Vec<S, V> vload_nt(const S* p) {
+    constexpr int B = (int)sizeof(S) * V;
+    if constexpr (B <= 16) {
+        using R = typename RawT<B>::t;
+        R r = __builtin_nontemporal_load(reinterpret_cast<const R*>(p));
+        return __builtin_bit_cast(Vec<S, V>, r);
+    } else {
+        Vec<S, V> out;
+        auto lo = vload_nt<S, V / 2>(p);
+        auto hi = vload_nt<S, V / 2>(p + V / 2);
+#pragma unroll
+        for (int i = 0; i < V / 2; ++i) {
+            out.v[i] = lo.v[i];
+            out.v[V / 2 + i] = hi.v[i];
+        }
+        return out;
+    }
+}
+template <class S, int V>
+__device__ __forceinline__ void vstore_nt(S* p, const Vec<S, V>& x) {
+    constexpr int B = (int)sizeof(S) * V;
+    if constexpr (B <= 16) {
+        using R = typename RawT<B>::t;
+        __builtin_nontemporal_store(__builtin_bit_cast(R, x), reinterpret_cast<R*>(p));
+    } else {
+        Vec<S, V / 2> lo, hi;
+#pragma unroll
+        for (int i = 0; i < V / 2; ++i) {
+            lo.v[i] = x.v[i];
+            hi.v[i] = x.v[V / 2 + i];
+        }
+        vstore_nt<S, V / 2>(p, lo);
+        vstore_nt<S, V / 2>(p + V / 2, hi);
+    }
+}
+
+// Element `i` of a row whose base address is wave-uniform: the byte offset is
+// formed in 32 bits so the access can use a scalar base plus a 32-bit vector
+// offset (one VGPR per access instead of a 64-bit address pair).
+template <class S>
+__device__ __forceinline__ const S* row_at(const S* row, int i) {
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(row) +
+                                      (uint32_t)(i * (int)sizeof(S)));
+}
+template <class S>
+__device__ __forceinline__ S* row_at(S* row, int i) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(row) + (uint32_t)(i * (int)sizeof(S)));
+}
+
 // ---- grid geometry shared by every kernel of one call --------------------
 struct Geo {
     int nx, ny, nz;        // interior extents (nz = layers for 2D)

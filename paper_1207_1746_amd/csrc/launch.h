@@ -58,8 +58,9 @@ hipError_t launch_reduce(const void* a, const void* b, int dtype, const Geo& g, 
                          hipStream_t s, int max_blocks, int* nblocks);
 
 // Integer image filters: box 5x5 (rounded mean) and 3x3 Laplacian.
+// `cy` rows per block (fast kernel).
 hipError_t launch_image(const uint8_t* img, uint8_t* box, int16_t* lap, const Geo& g,
-                        int lap_kind, hipStream_t s);
+                        int lap_kind, int cy, hipStream_t s);
 
 // Elementwise y = alpha * a + beta * b (b optional) with per-grid storage
 // types; and fill.  Used by the iterative-refinement driver.

@@ -16,6 +16,7 @@ template <class T_, class S_, int NDIM_, bool HAS_F>
 struct OpWJacobi {
     using T = T_; using SN = S_; using SA = S_; using SB = S_; using SO = S_;
     static constexpr int NF = 1, NA = HAS_F ? 1 : 0, NB = 0, NO = 1, NR = 1, R = 1, NDIM = NDIM_;
+    static constexpr bool SEPARABLE = false;
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
                                                  const double* p, T (&o)[1], double (&rv)[1],
@@ -49,6 +50,7 @@ struct OpWJacobi {
 struct OpPoissonResid {
     using T = double; using SN = double; using SA = double; using SB = double; using SO = float;
     static constexpr int NF = 1, NA = 1, NB = 0, NO = 1, NR = 1, R = 1, NDIM = 3;
+    static constexpr bool SEPARABLE = false;
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
                                                  const double* p, double (&o)[1], double (&rv)[1],
@@ -70,6 +72,7 @@ template <class T_, class S_>
 struct OpVarCoef7 {
     using T = T_; using SN = S_; using SA = S_; using SB = S_; using SO = S_;
     static constexpr int NF = 1, NA = 8, NB = 0, NO = 3, NR = 1, R = 1, NDIM = 3;
+    static constexpr bool SEPARABLE = false;
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply(const ST& st, const AV& c, const BV&,
                                                  const double*, T (&o)[3], double (&rv)[1],
@@ -141,16 +144,12 @@ template <class T_, class S_, int F>
 struct OpVC13Apply {
     using T = T_; using SN = S_; using SA = S_; using SB = S_; using SO = S_;
     static constexpr int NF = F, NA = 0, NB = 10, NO = F, NR = F, R = 2, NDIM = 3;
+    static constexpr bool SEPARABLE = true;  // field f's output reads only field f
     template <class ST, class AV, class BV>
-    __device__ __forceinline__ static void apply(const ST& st, const AV&, const BV& c,
-                                                 const double* p, T (&o)[F], double (&rv)[F],
-                                                 int) {
-        const T kappa = (T)p[0];
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            o[f] = vc13_Au<T>(st, f, c, kappa);
-            rv[f] = (double)o[f];
-        }
+    __device__ __forceinline__ static void apply_one(int, const ST& st, const AV&, const BV& c,
+                                                     const double* p, T& o, double& rv, int) {
+        o = vc13_Au<T>(st, 0, c, (T)p[0]);
+        rv = (double)o;
     }
 };
 
@@ -160,19 +159,15 @@ template <class T_, class SN_, class SA_, class SB_, int F>
 struct OpVC13Jacobi {
     using T = T_; using SN = SN_; using SA = SA_; using SB = SB_; using SO = SN_;
     static constexpr int NF = F, NA = F, NB = 10, NO = F, NR = F, R = 2, NDIM = 3;
+    static constexpr bool SEPARABLE = true;
     template <class ST, class AV, class BV>
-    __device__ __forceinline__ static void apply(const ST& st, const AV& gv, const BV& c,
-                                                 const double* p, T (&o)[F], double (&rv)[F],
-                                                 int operand) {
+    __device__ __forceinline__ static void apply_one(int f, const ST& st, const AV& gv, const BV& c,
+                                                     const double* p, T& o, double& rv, int operand) {
         const T kappa = (T)p[0], omega = (T)p[1];
-        const T D = vc13_diag<T>(c, kappa);
-        const T w = omega / D;
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            const T r = gv[f] - vc13_Au<T>(st, f, c, kappa);
-            o[f] = st.c[f] + w * r;
-            rv[f] = operand == RV_RESIDUAL ? (double)r : (double)(o[f] - st.c[f]);
-        }
+        const T w = omega / vc13_diag<T>(c, kappa);
+        const T r = gv[f] - vc13_Au<T>(st, 0, c, kappa);
+        o = st.c[0] + w * r;
+        rv = operand == RV_RESIDUAL ? (double)r : (double)(o - st.c[0]);
     }
 };
 
@@ -182,16 +177,12 @@ template <class SB_, int F>
 struct OpVC13Resid {
     using T = double; using SN = double; using SA = double; using SB = SB_; using SO = float;
     static constexpr int NF = F, NA = F, NB = 10, NO = F, NR = F, R = 2, NDIM = 3;
+    static constexpr bool SEPARABLE = true;
     template <class ST, class AV, class BV>
-    __device__ __forceinline__ static void apply(const ST& st, const AV& bv, const BV& c,
-                                                 const double* p, double (&o)[F],
-                                                 double (&rv)[F], int) {
-        const double kappa = p[0];
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            o[f] = bv[f] - vc13_Au<double>(st, f, c, kappa);
-            rv[f] = o[f];
-        }
+    __device__ __forceinline__ static void apply_one(int f, const ST& st, const AV& bv, const BV& c,
+                                                     const double* p, double& o, double& rv, int) {
+        o = bv[f] - vc13_Au<double>(st, 0, c, p[0]);
+        rv = o;
     }
 };
 

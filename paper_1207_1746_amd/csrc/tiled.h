@@ -8,9 +8,14 @@
 //     current plane is staged in LDS with its x and y halo for the in-plane
 //     neighbours.  Every input plane is therefore fetched from HBM once per
 //     sweep (plus a thin halo).
-//   * pointwise grids are streamed straight into registers.
-//   * the next plane's loads are issued before the current plane is computed
-//     (one plane of software prefetch).
+//   * pointwise grids are streamed straight into registers and outputs are
+//     written with streaming (non-temporal) accesses, so the single-use
+//     streams do not evict the neighbour-read planes other tiles re-read.
+//   * single-field operators issue the next plane's loads before the current
+//     plane is computed (one plane of software prefetch); operators with
+//     several neighbour-read fields skip it -- their register queues already
+//     hold F * (2R+1) planes, and halving the register footprint buys more
+//     resident waves, which hide the latency instead.
 //   * halo values outside the domain are synthesized from the boundary rule
 //     (no stored halo, no halo-fill pass).
 //   * an optional fused reduction of a per-point value (Section 5.2 fuse) is
@@ -49,7 +54,8 @@ __device__ __forceinline__ void load_nb(const S* base, const Geo& g, int gx, int
                                         T (&o)[V]) {
     const bool row_in = (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
     if (row_in && gx >= 0 && gx + V <= g.nx) {
-        Vec<S, V> v = vload<S, V>(base + (int64_t)z * g.pz + (int64_t)y * g.py + gx);
+        const S* row = base + ((int64_t)z * g.pz + (int64_t)y * g.py);
+        Vec<S, V> v = vload<S, V>(row_at(row, gx));
 #pragma unroll
         for (int i = 0; i < V; ++i) o[i] = from_s<T>(v.v[i]);
     } else {
@@ -60,12 +66,13 @@ __device__ __forceinline__ void load_nb(const S* base, const Geo& g, int gx, int
 
 // Pointwise row load; only rows/columns inside the interior are meaningful.
 // Rows are padded to 16 elements, so a vector starting inside the row stays
-// inside the allocation.
+// inside the allocation.  Pointwise grids are read once per sweep: streamed.
 template <class S, int V>
 __device__ __forceinline__ void load_pw(const S* base, const Geo& g, int gx, int y, int z,
                                         S (&o)[V]) {
     if ((unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz && gx < g.nx) {
-        Vec<S, V> v = vload<S, V>(base + (int64_t)z * g.pz + (int64_t)y * g.py + gx);
+        const S* row = base + ((int64_t)z * g.pz + (int64_t)y * g.py);
+        Vec<S, V> v = vload_nt<S, V>(row_at(row, gx));
 #pragma unroll
         for (int i = 0; i < V; ++i) o[i] = v.v[i];
     }
@@ -90,12 +97,15 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
     constexpr int CO = (16 / (int)sizeof(T)) > R ? (16 / (int)sizeof(T)) : R;  // aligned core column
     constexpr int LW = CO + TX + R;
     constexpr int LH = NW + 2 * R;
+    constexpr bool PF = NF == 1;  // software prefetch of the next plane
     static_assert(NW >= 2 * R, "need a wave per halo row");
 
     __shared__ __attribute__((aligned(16))) T lds[NF][LH][LW];
 
     const Geo& g = a.g;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is uniform across the wave: row base addresses then live
+    // in scalar registers and each lane adds only its 32-bit column offset
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int xt = tile % a.ntx;
     const int rest = tile / a.ntx;
     const int yt = rest % a.nty;
@@ -137,25 +147,35 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
         for (int i = 0; i < Op::NB; ++i) load_pw<SB, V>(static_cast<const SB*>(a.pb[i]), g, gx, gy, z, bo[i]);
     };
 
-    // warm-up: planes z0-RZ .. z0+RZ, halos and pointwise values of plane z0
+    // warm-up: planes z0-RZ .. z0+RZ (the last one in-loop without prefetch),
+    // halos and pointwise values of plane z0
 #pragma unroll
-    for (int s = 0; s < QD; ++s)
+    for (int s = 0; s < (PF ? QD : QD - 1); ++s)
 #pragma unroll
         for (int f = 0; f < NF; ++f)
             load_nb<T, SN, V>(static_cast<const SN*>(a.nb[f]), g, gx, gy, z0 - RZ + s, q[f][s]);
-    load_halo(z0, xh, yh);
-    load_point(z0, pa, pb);
+    if (PF) {
+        load_halo(z0, xh, yh);
+        load_point(z0, pa, pb);
+    }
 
     const bool row_ok = gy < g.ny;
 
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 1 < z1;
-        if (more) {
+        if (PF && more) {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
                 load_nb<T, SN, V>(static_cast<const SN*>(a.nb[f]), g, gx, gy, z + RZ + 1, qn[f]);
             load_halo(z + 1, xhn, yhn);
             load_point(z + 1, pan, pbn);
+        }
+        if (!PF) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                load_nb<T, SN, V>(static_cast<const SN*>(a.nb[f]), g, gx, gy, z + RZ, q[f][QD - 1]);
+            load_halo(z, xh, yh);
+            load_point(z, pa, pb);
         }
         // stage plane z in LDS: core row, x halo (edge lanes), y halo rows
 #pragma unroll
@@ -179,51 +199,68 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
 
         T res[NO][V];
         double redv[NR][V];
+        // gather field f's star at element v (x neighbours inside the lane's
+        // vector come from registers, the rest from the staged plane)
+        auto gather = [&](auto& st, int sf, int f, int v) {
+            st.c[sf] = q[f][RZ][v];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            Star<T, NF, R> st;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                st.c[f] = q[f][RZ][v];
-#pragma unroll
-                for (int r = 1; r <= R; ++r) {
-                    st.xm[f][r - 1] = (v - r >= 0) ? q[f][RZ][(v - r) >= 0 ? v - r : 0]
-                                                   : lds[f][R + w][ccol + v - r];
-                    st.xp[f][r - 1] = (v + r < V) ? q[f][RZ][(v + r) < V ? v + r : 0]
-                                                  : lds[f][R + w][ccol + v + r];
-                    st.ym[f][r - 1] = lds[f][R + w - r][ccol + v];
-                    st.yp[f][r - 1] = lds[f][R + w + r][ccol + v];
-                    if (RZ > 0) {
-                        st.zm[f][r - 1] = q[f][(RZ - r) >= 0 ? RZ - r : 0][v];
-                        st.zp[f][r - 1] = q[f][(RZ + r) < QD ? RZ + r : 0][v];
-                    } else {
-                        st.zm[f][r - 1] = T(0);
-                        st.zp[f][r - 1] = T(0);
-                    }
+            for (int r = 1; r <= R; ++r) {
+                st.xm[sf][r - 1] = (v - r >= 0) ? q[f][RZ][(v - r) >= 0 ? v - r : 0]
+                                                : lds[f][R + w][ccol + v - r];
+                st.xp[sf][r - 1] = (v + r < V) ? q[f][RZ][(v + r) < V ? v + r : 0]
+                                               : lds[f][R + w][ccol + v + r];
+                st.ym[sf][r - 1] = lds[f][R + w - r][ccol + v];
+                st.yp[sf][r - 1] = lds[f][R + w + r][ccol + v];
+                if (RZ > 0) {
+                    st.zm[sf][r - 1] = q[f][(RZ - r) >= 0 ? RZ - r : 0][v];
+                    st.zp[sf][r - 1] = q[f][(RZ + r) < QD ? RZ + r : 0][v];
+                } else {
+                    st.zm[sf][r - 1] = T(0);
+                    st.zp[sf][r - 1] = T(0);
                 }
             }
-            T av[NA], bv[NB], o[NO];
-            double rv[NR];
+        };
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T av[NA], bv[NB];
 #pragma unroll
             for (int i = 0; i < NA; ++i) av[i] = Op::NA > 0 ? from_s<T>(pa[i][v]) : T(0);
 #pragma unroll
             for (int i = 0; i < NB; ++i) bv[i] = Op::NB > 0 ? from_s<T>(pb[i][v]) : T(0);
-            Op::apply(st, av, bv, a.p, o, rv, a.operand);
+            if constexpr (Op::SEPARABLE) {
+                // one field at a time: only one star is live
 #pragma unroll
-            for (int i = 0; i < NO; ++i) res[i][v] = o[i];
+                for (int f = 0; f < NF; ++f) {
+                    Star<T, 1, R> st1;
+                    gather(st1, 0, f, v);
+                    double rv1;
+                    Op::apply_one(f, st1, av, bv, a.p, res[f][v], rv1, a.operand);
+                    redv[f][v] = rv1;
+                }
+            } else {
+                Star<T, NF, R> st;
 #pragma unroll
-            for (int i = 0; i < NR; ++i) redv[i][v] = rv[i];
+                for (int f = 0; f < NF; ++f) gather(st, f, f, v);
+                T o[NO];
+                double rv[NR];
+                Op::apply(st, av, bv, a.p, o, rv, a.operand);
+#pragma unroll
+                for (int i = 0; i < NO; ++i) res[i][v] = o[i];
+#pragma unroll
+                for (int i = 0; i < NR; ++i) redv[i][v] = rv[i];
+            }
         }
         // store outputs (vector when the whole vector is inside the row)
         if (row_ok) {
-            const int64_t off = (int64_t)z * g.pz + (int64_t)gy * g.py + gx;
+            const int64_t rowoff = (int64_t)z * g.pz + (int64_t)gy * g.py;
+            const int64_t off = rowoff + gx;
             if (gx + V <= g.nx) {
 #pragma unroll
                 for (int i = 0; i < NO; ++i) {
                     Vec<SO, V> vv;
 #pragma unroll
                     for (int v = 0; v < V; ++v) vv.v[v] = Store<SO>::cv(res[i][v]);
-                    vstore<SO, V>(static_cast<SO*>(a.out[i]) + off, vv);
+                    vstore_nt<SO, V>(row_at(static_cast<SO*>(a.out[i]) + rowoff, gx), vv);
                 }
                 if (RED) {
 #pragma unroll
@@ -247,7 +284,14 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
             }
         }
         __syncthreads();
-        if (more) {
+        if (!PF) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int s = 0; s + 1 < QD; ++s)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) q[f][s][v] = q[f][s + 1][v];
+        } else if (more) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
 #pragma unroll

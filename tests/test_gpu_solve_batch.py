@@ -178,9 +178,11 @@ def test_batch_f64_matches_solver_and_oracle(sctx):
 def test_batch_budget_admission(ctx):
     r = _req(40)
     _, f = W.poisson_fields(r)
-    b = G.Batch(ctx, max_slots=4, precision=G.PREC_F64, sweeps_per_step=8, hbm_budget=2 * 40 ** 3 * 8 * 3)
-    fp = b.footprint((40, 40, 40))
-    assert fp >= 3 * 40 ** 3 * 8
+    probe = G.Batch(ctx, max_slots=1, precision=G.PREC_F64, sweeps_per_step=8, hbm_budget=1 << 20)
+    fp = probe.footprint((40, 40, 40))
+    probe.close()
+    assert fp >= 3 * 40 ** 3 * 8  # u, f and the ping-pong grid (rows padded to 16 elements)
+    b = G.Batch(ctx, max_slots=4, precision=G.PREC_F64, sweeps_per_step=8, hbm_budget=2 * fp + fp // 2)
     grids = [(ctx.grid(f.shape, G.F64, halo=1).fill(0.0), ctx.grid(f.shape, G.F64, halo=0, data=f))
              for _ in range(3)]
     assert b.admit(*grids[0], r.h2) is not None
