@@ -30,15 +30,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stencil Gpts/s + HBM GB/s vs peak; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1207_1746_amd/csrc/tiled.h", "paper_1207_1746_amd/csrc/ops.h",
-                  "paper_1207_1746_amd/csrc/kcommon.h", "paper_1207_1746_amd/csrc/sweeps_common.h",
-                  "paper_1207_1746_amd/csrc/k_image.hip", "paper_1207_1746_amd/csrc/k_sweep_varcoef.hip",
-                  "paper_1207_1746_amd/csrc/k_sweep_wjacobi.hip"]
+_CS = "paper_1207_1746_amd/csrc/"
+KERNEL_SOURCES = {
+    "varcoef7_256_f32": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h",
+                                          "k_sweep_varcoef.hip")],
+    "wjacobi_f64": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h",
+                                     "k_sweep_wjacobi.hip")],
+    "image_8192_u8": [_CS + f for f in ("kcommon.h", "k_image.hip")],
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(workload_key: str = "varcoef7_256_f32") -> str:
+    """Hash of the sources the workload's dominant kernel is built from."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[workload_key]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -56,7 +61,7 @@ def measured_traffic(workload_key: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip("- *`").strip()] = v.strip().strip("`")
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(workload_key):
         return None
     try:
         return float(rec["bytes_per_launch"])
@@ -341,10 +346,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile", default=None, help="V,NW,cz override for the dominant kernel")
-    ap.add_argument("--print-kernel-hash", action="store_true")
+    ap.add_argument("--print-kernel-hash", action="store_true",
+                    help="print the source hash of the selected workload's dominant kernel")
     args = ap.parse_args()
     if args.print_kernel_hash:
-        print(kernel_hash())
+        print(kernel_hash(WORKLOADS[args.config].key))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",

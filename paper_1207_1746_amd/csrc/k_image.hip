@@ -4,7 +4,8 @@
 //   lap = N + S + E + W - 4 C  (or 8-neighbour - 8 C)    (int16 out)
 //
 // Fast kernel (width a multiple of 16, 4-neighbour Laplacian): each lane owns
-// 16 consecutive pixels of a row and marches down a chunk of rows.  A 5-row
+// 16 consecutive pixels of a row and marches down a chunk of rows, with two
+// rows of loads in flight ahead of the row being filtered.  A 5-row
 // queue holds the raw bytes (the lane's 16 plus 4 on each side), vertical
 // window sums are kept as running sums of packed 16-bit pairs (even / odd
 // byte lanes of each dword, so 32-bit adds never carry between halves), the
@@ -69,10 +70,12 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
         VO[k] = odd(q[0].d[k]) + odd(q[1].d[k]) + odd(q[2].d[k]) + odd(q[3].d[k]) + odd(q[4].d[k]);
     }
 
+    // two rows in flight ahead of the one being consumed
+    Row6 nxt1, nxt2;
+    if (y0 + 1 < y1) nxt1 = load_row6(img, g, x, y0 + 3, z);
     for (int y = y0; y < y1; ++y) {
-        Row6 nxt;
         const bool more = y + 1 < y1;
-        if (more) nxt = load_row6(img, g, x, y + 3, z);
+        if (y + 2 < y1) nxt2 = load_row6(img, g, x, y + 4, z);
 
         // box: horizontal 5-sums of the vertical sums, columns 4k..4k+3
         uint32_t AE[5], AO[5];  // AE[k+1] = (hi VE[k], lo VE[k+1]), k = -1..3
@@ -124,12 +127,13 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
         if (more) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                VE[k] = VE[k] + evn(nxt.d[k]) - evn(q[0].d[k]);
-                VO[k] = VO[k] + odd(nxt.d[k]) - odd(q[0].d[k]);
+                VE[k] = VE[k] + evn(nxt1.d[k]) - evn(q[0].d[k]);
+                VO[k] = VO[k] + odd(nxt1.d[k]) - odd(q[0].d[k]);
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) q[i] = q[i + 1];
-            q[4] = nxt;
+            q[4] = nxt1;
+            nxt1 = nxt2;
         }
     }
 }
