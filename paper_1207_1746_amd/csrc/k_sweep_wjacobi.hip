@@ -3,6 +3,7 @@
 
 namespace gk {
 
+// Blocks a tiled launch with this tile uses (both drivers: 64*V x NW x cz).
 int tiled_blocks(const Geo& g, const TileCfg& c) {
     const int ntx = (g.nx + 64 * c.V - 1) / (64 * c.V);
     const int nty = (g.ny + c.NW - 1) / c.NW;

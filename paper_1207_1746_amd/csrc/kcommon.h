@@ -7,6 +7,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gk {
 
 typedef __hip_bfloat16 bf16;
@@ -14,6 +16,20 @@ typedef _Float16 f16;
 
 enum { BC_DIRICHLET = 0, BC_PERIODIC = 1, BC_CLAMP = 2 };
 enum { R_SUM = 0, R_SUMSQ = 1, R_L2 = 2, R_MAXABS = 3, R_ALL_LE = 4 };
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1, so that
+// per-field register arrays are always indexed with constants.
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for_impl(Fn&& fn) {
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for_impl<I + 1, N>(fn);
+    }
+}
+template <int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+    static_for_impl<0, N>(fn);
+}
 
 // ---- conversions: storage type -> compute type and back -----------------
 template <class T> __device__ __forceinline__ T from_s(double v) { return (T)v; }

@@ -2,6 +2,7 @@
 #pragma once
 #include "launch.h"
 #include "ops.h"
+#include "ring13.h"
 
 namespace gk {
 
@@ -41,12 +42,42 @@ static hipError_t run7(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int*
     return hipErrorInvalidValue;
 }
 
-// (V, NW) shapes instantiated for the 13-point family (radius 2).
+template <class Op, int V>
+static hipError_t run_ring(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nblocks) {
+    a.ntx = (a.g.nx + 64 * V - 1) / (64 * V);
+    a.nty = (a.g.ny + 3) / 4;
+    a.cz = c.cz;
+    a.ncz = (a.g.nz + c.cz - 1) / c.cz;
+    const int n = a.ntx * a.nty * a.ncz;
+    *nblocks = n;
+    if (n == 0) return hipSuccess;
+    if (red) {
+        hipLaunchKernelGGL((ring13_sweep<Op, V, true>), dim3(n), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_reduce_finish(a.ra, n, s);
+    }
+    hipLaunchKernelGGL((ring13_sweep<Op, V, false>), dim3(n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// (V, NW) shapes instantiated for the 13-point family (radius 2).  Several
+// fields: the LDS-ring driver (NW = 4; V = 2 only for 16-bit storage, whose
+// ring fits twice); one field: the register-queue driver.
 template <class Op>
 static hipError_t run13(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
-    if (c.V == 1 && c.NW == 4) return run<Op, 1, 4>(a, c, red, s, nb);
-    if (c.V == 2 && c.NW == 4) return run<Op, 2, 4>(a, c, red, s, nb);
-    return hipErrorInvalidValue;
+    if constexpr (Op::NF > 1) {
+        if (c.NW != 4) return hipErrorInvalidValue;
+        if (c.V == 1) return run_ring<Op, 1>(a, c, red, s, nb);
+        if constexpr (sizeof(typename Op::SN) <= 2) {
+            if (c.V == 2) return run_ring<Op, 2>(a, c, red, s, nb);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        if (c.V == 1 && c.NW == 4) return run<Op, 1, 4>(a, c, red, s, nb);
+        if (c.V == 2 && c.NW == 4) return run<Op, 2, 4>(a, c, red, s, nb);
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace gk

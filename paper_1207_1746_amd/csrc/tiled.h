@@ -120,27 +120,28 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
 
     T q[NF][QD][V];
     T qn[NF][V];
-    T xh[NF][2 * R], xhn[NF][2 * R];
+    // x halo: lane 0 holds the R cells left of the tile, lane 63 the R cells
+    // right of it (one code path, so the values stay in registers)
+    const bool xh_lane = lane == 0 || lane == 63;
+    const int xh_x = lane == 0 ? x0 - R : x0 + TX;
+    const int xh_col = lane == 0 ? CO - R : CO + TX;
+    T xh[NF][R], xhn[NF][R];
     T yh[NF][V], yhn[NF][V];
     SA pa[NA][V], pan[NA][V];
     SB pb[NB][V], pbn[NB][V];
 
-    auto load_halo = [&](int z, T (&xo)[NF][2 * R], T (&yo)[NF][V]) {
+    auto load_halo = [&](int z, T (&xo)[NF][R], T (&yo)[NF][V]) __attribute__((always_inline)) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const SN* b = static_cast<const SN*>(a.nb[f]);
-            if (lane == 0) {
+            if (xh_lane) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) xo[f][r] = fetch_bc<T, SN>(b, g, x0 - R + r, gy, z);
-            }
-            if (lane == 63) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) xo[f][R + r] = fetch_bc<T, SN>(b, g, x0 + TX + r, gy, z);
+                for (int r = 0; r < R; ++r) xo[f][r] = fetch_bc<T, SN>(b, g, xh_x + r, gy, z);
             }
             if (has_halo_row) load_nb<T, SN, V>(b, g, gx, hy, z, yo[f]);
         }
     };
-    auto load_point = [&](int z, SA (&ao)[NA][V], SB (&bo)[NB][V]) {
+    auto load_point = [&](int z, SA (&ao)[NA][V], SB (&bo)[NB][V]) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < Op::NA; ++i) load_pw<SA, V>(static_cast<const SA*>(a.pa[i]), g, gx, gy, z, ao[i]);
 #pragma unroll
@@ -182,13 +183,9 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
             for (int v = 0; v < V; ++v) lds[f][R + w][ccol + v] = q[f][RZ][v];
-            if (lane == 0) {
+            if (xh_lane) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[f][R + w][CO - R + r] = xh[f][r];
-            }
-            if (lane == 63) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) lds[f][R + w][CO + TX + r] = xh[f][R + r];
+                for (int r = 0; r < R; ++r) lds[f][R + w][xh_col + r] = xh[f][r];
             }
             if (has_halo_row) {
 #pragma unroll
@@ -201,7 +198,7 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
         double redv[NR][V];
         // gather field f's star at element v (x neighbours inside the lane's
         // vector come from registers, the rest from the staged plane)
-        auto gather = [&](auto& st, int sf, int f, int v) {
+        auto gather = [&](auto& st, int sf, int f, int v) __attribute__((always_inline)) {
             st.c[sf] = q[f][RZ][v];
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
@@ -301,7 +298,7 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
 #pragma unroll
                 for (int v = 0; v < V; ++v) q[f][QD - 1][v] = qn[f][v];
 #pragma unroll
-                for (int r = 0; r < 2 * R; ++r) xh[f][r] = xhn[f][r];
+                for (int r = 0; r < R; ++r) xh[f][r] = xhn[f][r];
 #pragma unroll
                 for (int v = 0; v < V; ++v) yh[f][v] = yhn[f][v];
             }

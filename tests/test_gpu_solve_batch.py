@@ -210,3 +210,25 @@ def test_serving_loop_continuous_batching(sctx):
         assert _oracle_rel_residual(got, f, r.h2) <= 1e-8 * 1.01
         alone = _batch_solve(ctx, [r], G.PREC_F32_IR, 32)[0]
         assert np.array_equal(alone[0], got)
+
+
+def test_autotuner_picks_installs_and_caches(ctx, tmp_path):
+    from paper_1207_1746_amd import autotune as AT
+    shape = (24, 40, 200)
+    u = np.random.default_rng(2).standard_normal(shape)
+    gu = ctx.grid(shape, G.F64, halo=1, data=u)
+    go = ctx.grid(shape, G.F64, halo=1)
+    path = str(tmp_path / "tiles.json")
+    t = AT.Tuner(ctx, path)
+    rec = t.tune(G.K_WJACOBI, [gu], [go], p=(0.9, 1.0), reps=3)
+    assert tuple(rec["tile"]) == ctx.tile_get(G.K_WJACOBI, gu)
+    assert len(rec["tried"]) >= 8
+    t.save()
+    ctx.do_all(G.K_WJACOBI, [gu], [go], p=(0.9, 1.0))
+    tuned = go.numpy()
+    ctx.tile_clear()
+    ctx.do_all(G.K_WJACOBI, [gu], [go], p=(0.9, 1.0))
+    assert np.array_equal(go.numpy(), tuned)  # the tile never changes a do_all result
+    t2 = AT.Tuner(ctx, path)
+    assert t2.apply(G.K_WJACOBI, gu) and ctx.tile_get(G.K_WJACOBI, gu) == tuple(rec["tile"])
+    ctx.tile_clear()
