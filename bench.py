@@ -37,6 +37,9 @@ KERNEL_SOURCES = {
     "wjacobi_f64": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h",
                                      "k_sweep_wjacobi.hip")],
     "image_8192_u8": [_CS + f for f in ("kcommon.h", "k_image.hip")],
+    "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
+    "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ring13.h", "ops.h", "sweeps_common.h",
+                                  "k_sweep_vc13a.hip")],
 }
 
 
@@ -123,27 +126,33 @@ class VarCoef:
                 "grid": [self.n] * 3, "sweeps_per_step": self.sweeps, "reduce_every": self.every,
                 "launch": "tiled z-march, tile " + str(self.ctx.tile_get(self.G.K_VARCOEF7, self.gu))}
 
-    def cpu_baseline(self, budget_s=12.0):
+    def cpu_baseline(self, budget_s=10.0):
+        """The oracle on the same inputs: whole 100-sweep passes (restarting
+        from u0) until about budget_s of CPU work has been done."""
         import numpy as np
         import oracle
         u, c, s = self.host
-        x = u.astype(np.float64)
         cp = np.ascontiguousarray(np.stack([ci.astype(np.float64) for ci in c]))
         sd = s.astype(np.float64)
         t0 = time.perf_counter()
         done = 0
-        while done < self.sweeps:
-            x, r, _ = oracle.varcoef7_sweep(x, cp, sd)
-            done += 1
-            if done % self.every == 0:
-                oracle.sumsq(r)
+        while True:
+            x = u.astype(np.float64)
+            for k in range(1, self.sweeps + 1):
+                x, r, _ = oracle.varcoef7_sweep(x, cp, sd)
+                done += 1
+                if k % self.every == 0:
+                    oracle.sumsq(r)
+                if time.perf_counter() - t0 >= 3 * budget_s:
+                    break
             if time.perf_counter() - t0 >= budget_s:
                 break
         dt = time.perf_counter() - t0
         return {"value": round(self.points * done / dt / 1e9, 4), "unit": self.unit,
                 "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": f"FP64 oracle, first {done} of the {self.sweeps} sweeps on the same "
-                          f"{self.n}^3 inputs ({dt:.1f} s), residual norms every {self.every}"}
+                "sample": f"FP64 oracle, {done} sweeps ({done / self.sweeps:g} passes of the "
+                          f"{self.sweeps}-sweep workload) on the same {self.n}^3 inputs in {dt:.1f} s, "
+                          f"residual norms every {self.every}"}
 
 
 class Jacobi:
@@ -287,7 +296,129 @@ class Serve:
                 "serving": "continuous batching, F32 correction sweeps + F64 residual (refinement)"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image, "serve": Serve}
+class Reduce:
+    """Standalone do_reduce: L2 norm of a 512^3 FP64 grid (8 B per point)."""
+    key = "reduce_f64"
+    bytes_per_point = 8
+
+    def __init__(self, ctx, n=512):
+        import torch
+        import paper_1207_1746_amd as G
+        self.G = G
+        self.g = ctx.grid((n, n, n), G.F64, halo=0)
+        self.g.view.copy_(torch.rand(n, n, n, dtype=torch.float64, device="cuda"))
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ctx, self.n = ctx, n
+        self.points = n ** 3
+        self.units_per_step = self.points
+        self.unit = "Gpts/s"
+
+    def step(self, ev=None):
+        if ev is not None:
+            ev.begin()
+        self.ctx.do_reduce(self.G.R_L2, self.g, dev_result=self.res)
+        if ev is not None:
+            ev.end()
+
+    def config(self):
+        return {"workload": f"do_reduce L2 norm of a {self.n}^3 FP64 grid"}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import numpy as np
+        import oracle
+        x = self.g.view.cpu().numpy()
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < budget_s:
+            oracle.sumsq(x)
+            reps += 1
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * reps / dt / 1e9, 4), "unit": self.unit, "cores": 1,
+                "kind": "oracle", "sample": f"{reps} pairwise sums of squares in {dt:.1f} s"}
+
+
+class VC13:
+    """Fourth-order 13-point operator on 5 fields sharing 10 coefficient grids,
+    512^3: one apply per storage dtype (BF16, FP16, FP32; FP32 math), and an
+    FP64-residual iterative-refinement solve to 1e-10 in BF16 storage."""
+    key = "vc13_512"
+    bytes_per_point = 40  # BF16: 5 fields + 10 coefficients read, 5 outputs written, 2 B each
+
+    def __init__(self, ctx, n=512):
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G, self.W = G, W
+        self.ctx, self.n = ctx, n
+        self.c, self.b = W.vc13_grids(n)
+        self.fields = W.vc13_fields(n)
+        shp = (n, n, n)
+        self.gc = [ctx.grid(shp, G.BF16, halo=0, data=x) for x in self.c]
+        self.gf = [ctx.grid(shp, G.BF16, halo=2, data=x) for x in self.fields]
+        self.go = [ctx.grid(shp, G.BF16, halo=0) for _ in range(5)]
+        self.points = n ** 3
+        self.units_per_step = self.points
+        self.unit = "Gpts/s"
+        self.extra = {}
+
+    def step(self, ev=None):
+        if ev is not None:
+            ev.begin()
+        self.ctx.do_all(self.G.K_VC13_APPLY, self.gf + self.gc, self.go, p=(self.W.VC13_KAPPA, 0, 5))
+        if ev is not None:
+            ev.end()
+
+    def after(self):
+        """Other storage types and the refinement solve (reported beside the value)."""
+        import torch
+        G, W, n = self.G, self.W, self.n
+        shp = (n, n, n)
+        out = {}
+        for dt, name, es in ((G.F16, "f16", 2), (G.F32, "f32", 4)):
+            gc = [self.ctx.grid(shp, dt, halo=0, data=x) for x in self.c]
+            gf = [self.ctx.grid(shp, dt, halo=2, data=x) for x in self.fields]
+            go = [self.ctx.grid(shp, dt, halo=0) for _ in range(5)]
+            fn = lambda: self.ctx.do_all(G.K_VC13_APPLY, gf + gc, go, p=(W.VC13_KAPPA, 0, 5))
+            fn()
+            sync()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                fn()
+            b.record()
+            sync()
+            ms = a.elapsed_time(b) / 5
+            out[f"apply_{name}"] = {"ms": round(ms, 3), "Gpts_s": round(n ** 3 / ms / 1e6, 2),
+                                    "GBs": round(20 * es * n ** 3 / ms / 1e6, 1)}
+            del gc, gf, go
+            torch.cuda.empty_cache()
+        gx = [self.ctx.grid(shp, G.F64, halo=2).fill(0.0) for _ in range(5)]
+        gb = [self.ctx.grid(shp, G.F64, halo=0, data=x) for x in self.b]
+        st = self.ctx.solve(G.K_VC13_APPLY, gx, gb, self.gc, kappa=W.VC13_KAPPA, rtol=1e-10, check_every=8,
+                            precision=G.PREC_BF16_IR, inner_sweeps=16)
+        out["refinement_bf16_to_1e-10"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in st.items()}
+        self.extra = out
+
+    def config(self):
+        return {"workload": f"13-point 4th-order operator, 5 fields + 10 coefficient grids, {self.n}^3, "
+                            "BF16 storage / FP32 math (apply)", "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        import numpy as np
+        x = self.fields[0].astype(np.float64)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < budget_s:
+            oracle.vc13_apply(x, self.c, self.W.VC13_KAPPA)
+            reps += 1
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * reps / 5 / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} single-field FP64 applies in {dt:.1f} s (scaled to 5 fields)"}
+
+
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image, "serve": Serve, "reduce": Reduce,
+             "vc13": VC13}
 
 
 class KernelEvents:
@@ -363,9 +494,10 @@ def main():
     wl = WORKLOADS[args.config](ctx)
     if args.tile:
         V, NW, cz = (int(v) for v in args.tile.split(","))
-        kind = {"varcoef": G.K_VARCOEF7, "jacobi": G.K_WJACOBI}.get(args.config)
+        kind = {"varcoef": G.K_VARCOEF7, "jacobi": G.K_WJACOBI, "image": G.K_IMG_BOX5_LAP}.get(args.config)
         if kind is not None:
-            ctx.tile_set(kind, wl.gu if args.config == "varcoef" else wl.a, (V, NW, cz))
+            ref = {"varcoef": lambda: wl.gu, "jacobi": lambda: wl.a, "image": lambda: wl.gi}[args.config]()
+            ctx.tile_set(kind, ref, (V, NW, cz))
     stream = ctx.stream
     if args.config == "serve":
         return serve_main(args, ctx, wl)
@@ -404,11 +536,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"varcoef": "f32", "jacobi": "f64", "image": "u8"}[args.config],
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "image": "u8", "reduce": "f64", "vc13": "bf16"}[args.config],
         "data": "synthetic (seeded)",
         "config": wl.config(),
-        "hbm_gbs_step": round(per_launch_bytes * wl.units_per_step / wl.points * args.steps / sec / 1e9, 2)
-        if args.config != "image" else round(per_launch_bytes * args.steps / sec / 1e9, 2),
+        "hbm_gbs_step": round(per_launch_bytes * wl.units_per_step / wl.points * args.steps / sec / 1e9, 2),
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 2),
@@ -422,6 +553,9 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if hasattr(wl, "after"):
+        wl.after()
+        out["extra"] = wl.extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = wl.cpu_baseline()
     ctx.end()

@@ -314,7 +314,15 @@ int gscl_batch_admit(gscl_batch *b, gscl_grid *u, const gscl_grid *f, double h2,
 int gscl_batch_step(gscl_batch *b);
 /* Copy slot states to the host (synchronizes) and list finished slots. */
 int gscl_batch_poll(gscl_batch *b, int *done, int cap, int *n_done);
-/* Release a finished (or running: cancel) slot; its answer is in its u grid. */
+/* Lagged poll: wait only until the step before the most recent one has
+ * finished (one step stays queued on the device) and list the slots that had
+ * finished by then.  A server that alternates step / lagged poll / retire /
+ * admit keeps the GPU busy while it does its host work. */
+int gscl_batch_poll_lagged(gscl_batch *b, int *done, int cap, int *n_done);
+/* Release a finished (or running: cancel) slot; its answer is in its u grid.
+ * For a slot reported finished by a poll this does not synchronize (finished
+ * slots are skipped by queued steps); cancelling a running slot drains the
+ * stream first. */
 int gscl_batch_retire(gscl_batch *b, int slot, gscl_slot_stats *stats);
 int gscl_batch_destroy(gscl_batch *b);
 

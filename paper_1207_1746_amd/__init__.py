@@ -106,6 +106,7 @@ _SIGS = {
     "gscl_batch_admit": (ctypes.c_int, [_vp, _vp, _vp, _f64, _P(ctypes.c_int)]),
     "gscl_batch_step": (ctypes.c_int, [_vp]),
     "gscl_batch_poll": (ctypes.c_int, [_vp, _P(ctypes.c_int), ctypes.c_int, _P(ctypes.c_int)]),
+    "gscl_batch_poll_lagged": (ctypes.c_int, [_vp, _P(ctypes.c_int), ctypes.c_int, _P(ctypes.c_int)]),
     "gscl_batch_retire": (ctypes.c_int, [_vp, ctypes.c_int, _P(SlotStats)]),
     "gscl_batch_destroy": (ctypes.c_int, [_vp]),
     "gscl_last_error": (ctypes.c_char_p, []),
@@ -437,10 +438,13 @@ class Batch:
     def step(self):
         check(lib().gscl_batch_step(self.handle), "gscl_batch_step")
 
-    def poll(self) -> list[int]:
+    def poll(self, lagged: bool = False) -> list[int]:
+        """Finished slots.  lagged=True waits only for the step before the
+        latest one (the device keeps working meanwhile)."""
         arr = (ctypes.c_int * self.max_slots)()
         n = ctypes.c_int(0)
-        check(lib().gscl_batch_poll(self.handle, arr, self.max_slots, ctypes.byref(n)), "gscl_batch_poll")
+        fn = lib().gscl_batch_poll_lagged if lagged else lib().gscl_batch_poll
+        check(fn(self.handle, arr, self.max_slots, ctypes.byref(n)), "gscl_batch_poll")
         return [arr[i] for i in range(min(n.value, self.max_slots))]
 
     def retire(self, slot: int) -> dict:

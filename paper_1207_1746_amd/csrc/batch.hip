@@ -249,6 +249,12 @@ struct gscl_batch {
     BState* h_state;    // pinned
     BHeader* h_hdr;     // pinned
     hipEvent_t upload_done;
+    BState* h_snap[2];  // pinned per-step state snapshots (double-buffered)
+    hipEvent_t snap_done[2];
+    int64_t steps;      // steps enqueued
+    int64_t snap_step;  // step index of the last snapshot read by a lagged poll (-1: none)
+    std::vector<int64_t> admit_step;  // steps enqueued when the slot was admitted
+    std::vector<int> known_state;     // final state seen in a snapshot (0: not final)
     std::vector<bool> used;
     std::vector<BSlot> slot;       // by id
     std::vector<size_t> work_bytes;
@@ -305,6 +311,8 @@ extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_ba
         hipHostFree(b->h_slots);
         hipHostFree(b->h_state);
         hipHostFree(b->h_hdr);
+        hipHostFree(b->h_snap[0]);
+        hipHostFree(b->h_snap[1]);
         delete b;
         return GSCL_ERR_HIP;
     };
@@ -323,11 +331,20 @@ extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_ba
     if ((e = hipHostMalloc(&b->h_state, sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipHostMalloc");
     if ((e = hipHostMalloc(&b->h_hdr, sizeof(BHeader))) != hipSuccess) return fail(e, "hipHostMalloc");
     if ((e = hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming)) != hipSuccess) return fail(e, "hipEventCreate");
+    for (int k = 0; k < 2; ++k) {
+        if ((e = hipHostMalloc(&b->h_snap[k], sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipHostMalloc");
+        if ((e = hipEventCreateWithFlags(&b->snap_done[k], hipEventDisableTiming)) != hipSuccess)
+            return fail(e, "hipEventCreate");
+    }
+    b->steps = 0;
+    b->snap_step = -1;
     if ((e = hipMemset(b->d_state, 0, sizeof(BState) * ms)) != hipSuccess) return fail(e, "hipMemset");
     memset(b->h_hdr, 0, sizeof(BHeader));
     if ((e = hipMemcpy(b->d_hdr, b->h_hdr, sizeof(BHeader), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "hipMemcpy");
     b->used.assign(ms, false);
+    b->admit_step.assign(ms, 0);
+    b->known_state.assign(ms, 0);
     b->slot.assign(ms, BSlot{});
     b->work_bytes.assign(ms, 0);
     b->work_ptr.assign(ms, nullptr);
@@ -435,6 +452,8 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     b->work_bytes[id] = wb;
     b->foot[id] = fp;
     b->footprint_used += fp;
+    b->admit_step[id] = b->steps;
+    b->known_state[id] = 0;
     // state: running, ||f||^2 on the device, d = 0 for refinement
     hipLaunchKernelGGL(batch_state_init, dim3(1), dim3(64), 0, c->stream, b->d_state, id);
     GSCL_HIP(hipGetLastError());
@@ -483,13 +502,28 @@ static int enqueue_step(gscl_batch* b) {
     return GSCL_OK;
 }
 
+// After every step a snapshot of the slot states goes to pinned memory, so a
+// lagged poll can read step k-1's states while step k runs.
+static int snapshot(gscl_batch* b) {
+    gscl_ctx* c = b->ctx;
+    const int k = (int)(b->steps & 1);
+    GSCL_HIP(hipMemcpyAsync(b->h_snap[k], b->d_state, sizeof(BState) * b->desc.max_slots,
+                            hipMemcpyDeviceToHost, c->stream));
+    GSCL_HIP(hipEventRecord(b->snap_done[k], c->stream));
+    b->steps += 1;
+    return GSCL_OK;
+}
+
 extern "C" int gscl_batch_step(gscl_batch* b) {
     if (!batch_ok(b)) return gscl_fail(GSCL_ERR_ARG, "invalid batch");
     gscl_ctx* c = b->ctx;
     if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "batch needs an active context");
     int rc;
     if (b->dirty && (rc = upload_table(b))) return rc;
-    if (!b->desc.use_graph || !c->stream) return enqueue_step(b);
+    if (!b->desc.use_graph || !c->stream) {
+        if ((rc = enqueue_step(b))) return rc;
+        return snapshot(b);
+    }
     if (!b->graph) {
         if ((rc = gscl_graph_begin(c))) return rc;
         int e = enqueue_step(b);
@@ -499,7 +533,32 @@ extern "C" int gscl_batch_step(gscl_batch* b) {
         if (e2) return e2;
         b->graph = g;
     }
-    return gscl_graph_launch(c, b->graph);
+    if ((rc = gscl_graph_launch(c, b->graph))) return rc;
+    return snapshot(b);
+}
+
+extern "C" int gscl_batch_poll_lagged(gscl_batch* b, int* done, int cap, int* n_done) {
+    if (!batch_ok(b) || !n_done || (cap > 0 && !done)) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
+    *n_done = 0;
+    if (b->steps == 0) return GSCL_OK;
+    // wait for the step before the latest (or the only one)
+    const int64_t k = b->steps >= 2 ? b->steps - 2 : b->steps - 1;
+    GSCL_HIP(hipEventSynchronize(b->snap_done[k & 1]));
+    const BState* snap = b->h_snap[k & 1];
+    b->snap_step = k;
+    int n = 0;
+    for (int id = 0; id < b->desc.max_slots; ++id) {
+        // a snapshot speaks for a slot only if the slot was admitted before that step
+        if (!b->used[id] || b->admit_step[id] > k) continue;
+        if (snap[id].state >= 2) {
+            b->known_state[id] = snap[id].state;
+            b->h_state[id] = snap[id];
+            if (n < cap) done[n] = id;
+            ++n;
+        }
+    }
+    *n_done = n;
+    return GSCL_OK;
 }
 
 extern "C" int gscl_batch_poll(gscl_batch* b, int* done, int cap, int* n_done) {
@@ -512,6 +571,7 @@ extern "C" int gscl_batch_poll(gscl_batch* b, int* done, int cap, int* n_done) {
     int n = 0;
     for (int id = 0; id < ms; ++id)
         if (b->used[id] && b->h_state[id].state >= 2) {
+            b->known_state[id] = b->h_state[id].state;
             if (n < cap) done[n] = id;
             ++n;
         }
@@ -524,10 +584,16 @@ extern "C" int gscl_batch_retire(gscl_batch* b, int id, gscl_slot_stats* st) {
     if (!b->used[id]) return gscl_fail(GSCL_ERR_ARG, "slot %d is not admitted", id);
     gscl_ctx* c = b->ctx;
     if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "retire inside graph capture");
-    // make sure no queued step still touches the slot's grids
-    GSCL_HIP(hipStreamSynchronize(c->stream));
     BState bs;
-    GSCL_HIP(hipMemcpy(&bs, &b->d_state[id], sizeof bs, hipMemcpyDeviceToHost));
+    if (b->known_state[id] >= 2) {
+        // finished in a snapshot: the kernels skip a finished slot, so queued
+        // steps no longer touch its grids and its memory can be reused now
+        bs = b->h_state[id];
+    } else {
+        // cancel of a running slot: drain the queue first
+        GSCL_HIP(hipStreamSynchronize(c->stream));
+        GSCL_HIP(hipMemcpy(&bs, &b->d_state[id], sizeof bs, hipMemcpyDeviceToHost));
+    }
     if (st) {
         st->state = bs.state;
         st->reserved = 0;
@@ -538,6 +604,7 @@ extern "C" int gscl_batch_retire(gscl_batch* b, int id, gscl_slot_stats* st) {
     b->arena.release(b->work_ptr[id], b->work_bytes[id]);
     b->footprint_used -= b->foot[id];
     b->used[id] = false;
+    b->known_state[id] = 0;
     b->dirty = true;
     return GSCL_OK;
 }
@@ -555,6 +622,10 @@ extern "C" int gscl_batch_destroy(gscl_batch* b) {
     hipHostFree(b->h_slots);
     hipHostFree(b->h_state);
     hipHostFree(b->h_hdr);
+    for (int k = 0; k < 2; ++k) {
+        hipHostFree(b->h_snap[k]);
+        hipEventDestroy(b->snap_done[k]);
+    }
     b->magic = 0;
     delete b;
     return GSCL_OK;

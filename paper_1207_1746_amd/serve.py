@@ -68,8 +68,10 @@ class ServeReport:
 class SolveServer:
     def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
                  rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
-                 hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7):
+                 hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7,
+                 pipelined: bool = True):
         self.ctx = ctx
+        self.pipelined = pipelined
         self.batch = G.Batch(ctx, max_slots=max_slots, precision=precision,
                              sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,
                              rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps)
@@ -117,7 +119,10 @@ class SolveServer:
             occ.append(len(running))
             self.batch.step()
             steps += 1
-            for slot in self.batch.poll():
+            # one step stays queued while finished requests are retired and new
+            # ones admitted; drain with a full poll once nothing new can arrive
+            lag = self.pipelined and (i < len(pending) or queue or len(running) > 1)
+            for slot in self.batch.poll(lagged=lag):
                 job = running.pop(slot)
                 st = self.batch.retire(slot)
                 job.done_at = time.perf_counter() - t0
