@@ -38,7 +38,7 @@ KERNEL_SOURCES = {
                                      "k_sweep_wjacobi.hip")],
     "image_8192_u8": [_CS + f for f in ("kcommon.h", "k_image.hip")],
     "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
-    "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ring13.h", "ops.h", "sweeps_common.h",
+    "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "zq13.h", "ops.h", "sweeps_common.h",
                                   "k_sweep_vc13a.hip")],
 }
 

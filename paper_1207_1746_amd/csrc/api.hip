@@ -226,8 +226,8 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
         t.V = nx >= 128 ? 2 : 1;
     else
         t.V = nx >= 256 ? 4 : (nx >= 128 ? 2 : 1);
-    // multi-field radius-2 kinds run the LDS-ring driver: one element per
-    // lane (its ring then fits several blocks per CU)
+    // radius-2 kinds: one element per lane (the multi-field z queues then fit
+    // four waves per SIMD)
     if (r2) t.V = 1;
     t.NW = 4;
     const int64_t ntx = (nx + 64 * t.V - 1) / (64 * t.V);

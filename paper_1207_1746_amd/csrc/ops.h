@@ -139,6 +139,47 @@ __device__ __forceinline__ T vc13_diag(const CV& c, T kappa) {
     return c[0] + kappa * sum;
 }
 
+// The same operator regrouped for drivers that evaluate several fields per
+// point: with a_{d+-} = (4/3) kappa c_{d+-}, b_d = kappa c_{d2} / 12 and
+// D = c0 + sum_d (a_{d+} + a_{d-} - 2 b_d) (the diagonal of A),
+//   (A u)(x) = D u - sum_d [a_{d+} u(x+e_d) + a_{d-} u(x-e_d) - b_d (u(x+2e_d) + u(x-2e_d))].
+// The combinations depend only on the coefficients, so they are formed once
+// per point and shared by the fields.
+template <class T>
+struct VC13Pre {
+    T d, ap[3], am[3], b[3];
+    T w;  // omega / D (Jacobi sweeps)
+};
+template <class T, class CV>
+__device__ __forceinline__ VC13Pre<T> vc13_prep(const CV& c, const double* p, bool with_w) {
+    const T k43 = (T)(p[0] * (4.0 / 3.0)), k12 = (T)(p[0] / 12.0);
+    VC13Pre<T> q;
+    T dsum = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        q.ap[d] = k43 * c[1 + 2 * d];
+        q.am[d] = k43 * c[2 + 2 * d];
+        q.b[d] = k12 * c[7 + d];
+        dsum = dsum + ((q.ap[d] + q.am[d]) - T(2) * q.b[d]);
+    }
+    q.d = c[0] + dsum;
+    q.w = with_w ? (T)p[1] / q.d : T(0);
+    return q;
+}
+template <class T, class ST>
+__device__ __forceinline__ T vc13_Au_pre(const ST& st, const VC13Pre<T>& q) {
+    T s = q.ap[0] * st.xp[0][0];
+    s = s + q.am[0] * st.xm[0][0];
+    s = s - q.b[0] * (st.xp[0][1] + st.xm[0][1]);
+    s = s + q.ap[1] * st.yp[0][0];
+    s = s + q.am[1] * st.ym[0][0];
+    s = s - q.b[1] * (st.yp[0][1] + st.ym[0][1]);
+    s = s + q.ap[2] * st.zp[0][0];
+    s = s + q.am[2] * st.zm[0][0];
+    s = s - q.b[2] * (st.zp[0][1] + st.zm[0][1]);
+    return q.d * st.c[0] - s;
+}
+
 // v_f = A u_f for F fields sharing the coefficients.  p[0] = kappa.
 template <class T_, class S_, int F>
 struct OpVC13Apply {
@@ -149,6 +190,17 @@ struct OpVC13Apply {
     __device__ __forceinline__ static void apply_one(int, const ST& st, const AV&, const BV& c,
                                                      const double* p, T& o, double& rv, int) {
         o = vc13_Au<T>(st, 0, c, (T)p[0]);
+        rv = (double)o;
+    }
+    using Pre = VC13Pre<T>;
+    template <class BV>
+    __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+        return vc13_prep<T>(c, p, false);
+    }
+    template <class ST, class AV>
+    __device__ __forceinline__ static void apply_pre(int, const ST& st, const AV&, const Pre& q,
+                                                     const double*, T& o, double& rv, int) {
+        o = vc13_Au_pre<T>(st, q);
         rv = (double)o;
     }
 };
@@ -169,6 +221,18 @@ struct OpVC13Jacobi {
         o = st.c[0] + w * r;
         rv = operand == RV_RESIDUAL ? (double)r : (double)(o - st.c[0]);
     }
+    using Pre = VC13Pre<T>;
+    template <class BV>
+    __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+        return vc13_prep<T>(c, p, true);
+    }
+    template <class ST, class AV>
+    __device__ __forceinline__ static void apply_pre(int f, const ST& st, const AV& gv, const Pre& q,
+                                                     const double*, T& o, double& rv, int operand) {
+        const T r = gv[f] - vc13_Au_pre<T>(st, q);
+        o = st.c[0] + q.w * r;
+        rv = operand == RV_RESIDUAL ? (double)r : (double)(o - st.c[0]);
+    }
 };
 
 // r_f = b_f - A x_f in FP64, stored as F32.  nb = x (F64), A = b (F64),
@@ -182,6 +246,17 @@ struct OpVC13Resid {
     __device__ __forceinline__ static void apply_one(int f, const ST& st, const AV& bv, const BV& c,
                                                      const double* p, double& o, double& rv, int) {
         o = bv[f] - vc13_Au<double>(st, 0, c, p[0]);
+        rv = o;
+    }
+    using Pre = VC13Pre<double>;
+    template <class BV>
+    __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+        return vc13_prep<double>(c, p, false);
+    }
+    template <class ST, class AV>
+    __device__ __forceinline__ static void apply_pre(int f, const ST& st, const AV& bv, const Pre& q,
+                                                     const double*, double& o, double& rv, int) {
+        o = bv[f] - vc13_Au_pre<double>(st, q);
         rv = o;
     }
 };
