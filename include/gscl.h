@@ -229,7 +229,9 @@ int gscl_do_reduce(gscl_ctx *ctx, const gscl_reduce_desc *rd, const gscl_grid *a
  * an x-by-y tile and the block marches cz planes (or layers) in z.  The
  * library picks a shape from the extents; a tuner may override it for one
  * (kind, dtype, extents) key of a context.  V in {1,2,4} (radius-2 kinds
- * {1,2}; F64 {1,2}), NW in {4,8} (radius-2 kinds 4), cz >= 1. */
+ * {1,2} with FP32 math, 1 with FP64 math; F64 {1,2}), NW in {4,8} (radius-2
+ * kinds: 4 for one field, {4,6,8} for five fields), cz >= 1.  A shape with no
+ * kernel for the kind is reported by the launch as GSCL_ERR_UNSUPPORTED. */
 typedef struct { int32_t V, NW, cz; } gscl_tile;
 int gscl_tile_get(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, gscl_tile *out);
 int gscl_tile_set(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, const gscl_tile *tile);

@@ -29,7 +29,9 @@ def candidates(kind: int, dtype: int, nz: int) -> list[tuple[int, int, int]]:
     if kind == G.K_IMG_BOX5_LAP:
         return [(4, 4, cy) for cy in (4, 8, 16, 32, 64)]
     if kind in RADIUS2:
-        vs, nws = (1, 2), (4,)
+        # one-field operators run NW = 4 only; shapes without a kernel are
+        # skipped by the tuner (the launch reports them as unsupported)
+        vs, nws = ((1,) if dtype == G.F64 else (1, 2)), (4, 6, 8)
     elif dtype == G.F64:
         vs, nws = (1, 2), (4, 8)
     else:

@@ -218,17 +218,15 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
     const bool r2 = kind == GSCL_K_VC13_APPLY || kind == GSCL_K_VC13_JACOBI || kind == GSCL_K_VC13_RESID;
     // Defaults from tile sweeps on MI355X: 16-byte lanes (V = 4 for F32, V = 2
     // for F64), 4 waves per block, and short z chunks so that a launch has
-    // several thousand blocks (about 8-16 per CU); radius-2 multi-field
-    // kernels use one element per lane to keep their register queues small.
+    // several thousand blocks (about 8-16 per CU).  Radius-2 kinds: two
+    // elements per lane with FP32 math, one with FP64 math (their register
+    // queues hold five planes per field).
     if (r2)
-        t.V = nx >= 128 ? 2 : 1;
+        t.V = (dtype == GSCL_F64 || nx < 128) ? 1 : 2;
     else if (dtype == GSCL_F64)
         t.V = nx >= 128 ? 2 : 1;
     else
         t.V = nx >= 256 ? 4 : (nx >= 128 ? 2 : 1);
-    // radius-2 kinds: one element per lane (the multi-field z queues then fit
-    // four waves per SIMD)
-    if (r2) t.V = 1;
     t.NW = 4;
     const int64_t ntx = (nx + 64 * t.V - 1) / (64 * t.V);
     const int64_t nty = (d.n[1] + t.NW - 1) / t.NW;
@@ -254,7 +252,7 @@ static gk::TileCfg reduce_tile(gk::TileCfg t, const gscl_grid_desc& d) {
 extern "C" int gscl_tile_set(gscl_ctx* c, int kind, const gscl_grid_desc* gd, const gscl_tile* t) {
     if (!ctx_ok(c) || !gd || !t) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
     if (t->V != 1 && t->V != 2 && t->V != 4) return gscl_fail(GSCL_ERR_ARG, "V must be 1, 2 or 4");
-    if (t->NW != 4 && t->NW != 8) return gscl_fail(GSCL_ERR_ARG, "NW must be 4 or 8");
+    if (t->NW != 4 && t->NW != 6 && t->NW != 8) return gscl_fail(GSCL_ERR_ARG, "NW must be 4, 6 or 8");
     if (t->cz < 1) return gscl_fail(GSCL_ERR_ARG, "cz must be >= 1");
     gscl_grid_desc d = *gd;
     int rc = resolve_layout(&d);
@@ -548,6 +546,14 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
                 return rc;
             if (op->kind != GSCL_K_VC13_APPLY && (rc = check_dtypes(in, F, F, dg, "right-hand side"))) return rc;
             if (!is_float(dnb) || !is_float(dc)) return gscl_fail(GSCL_ERR_DTYPE, "VC13 needs floating-point grids");
+            if (F > 1) {  // the five-field kernels address grids with 32-bit byte offsets
+                for (int i = 0; i < n_in; ++i)
+                    if (in[i]->bytes >= ((size_t)1 << 32))
+                        return gscl_fail(GSCL_ERR_UNSUPPORTED, "five-field VC13 kinds need grids under 4 GiB each");
+                for (int i = 0; i < n_out; ++i)
+                    if (out[i]->bytes >= ((size_t)1 << 32))
+                        return gscl_fail(GSCL_ERR_UNSUPPORTED, "five-field VC13 kinds need grids under 4 GiB each");
+            }
             double p[8] = {op->p[0], op->p[1], (double)F, 0, 0, 0, 0, 0};
             fill_targs(a, g0, p);
             for (int f = 0; f < F; ++f) a.nb[f] = in[f]->ptr;

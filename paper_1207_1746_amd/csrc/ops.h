@@ -1,6 +1,11 @@
 // Stencil operators for the tiled do_all driver.  Each operator states its
 // access traits (how many grids it reads at offsets, how many pointwise, how
 // many it writes) and computes one point from a Star neighbourhood.
+//
+// Every operator body turns off floating-point contraction and writes the
+// fused multiply-adds it wants explicitly: the compiler would otherwise pick
+// which product of a sum to fuse from the shape of the surrounding code, and
+// the same point could round differently under different tile shapes.
 #pragma once
 
 #include "tiled.h"
@@ -21,6 +26,7 @@ struct OpWJacobi {
     __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
                                                  const double* p, T (&o)[1], double (&rv)[1],
                                                  int operand) {
+#pragma clang fp contract(off)
         const T u = st.c[0];
         T s = st.xp[0][0] + st.xm[0][0];
         s = s + st.yp[0][0];
@@ -55,6 +61,7 @@ struct OpPoissonResid {
     __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
                                                  const double* p, double (&o)[1], double (&rv)[1],
                                                  int) {
+#pragma clang fp contract(off)
         double s = st.xp[0][0] + st.xm[0][0];
         s = s + st.yp[0][0];
         s = s + st.ym[0][0];
@@ -77,6 +84,7 @@ struct OpVarCoef7 {
     __device__ __forceinline__ static void apply(const ST& st, const AV& c, const BV&,
                                                  const double*, T (&o)[3], double (&rv)[1],
                                                  int operand) {
+#pragma clang fp contract(off)
         const T u = st.c[0];
         const T xp = st.xp[0][0], xm = st.xm[0][0], yp = st.yp[0][0], ym = st.ym[0][0];
         const T zp = st.zp[0][0], zm = st.zm[0][0];
@@ -110,6 +118,7 @@ struct OpVarCoef7 {
 // c0, c_{x+}, c_{x-}, c_{y+}, c_{y-}, c_{z+}, c_{z-}, c_{x2}, c_{y2}, c_{z2}).
 template <class T, class ST, class CV>
 __device__ __forceinline__ T vc13_Au(const ST& st, int f, const CV& c, T kappa) {
+#pragma clang fp contract(off)
     const T u = st.c[f];
     const T ax = T(4) / T(3), bx = T(1) / T(12);
     T sum = T(0);
@@ -132,6 +141,7 @@ __device__ __forceinline__ T vc13_Au(const ST& st, int f, const CV& c, T kappa) 
 }
 template <class T, class CV>
 __device__ __forceinline__ T vc13_diag(const CV& c, T kappa) {
+#pragma clang fp contract(off)
     const T ax = T(4) / T(3), b6 = T(1) / T(6);
     T sum = ax * (c[1] + c[2]) - b6 * c[7];
     sum = sum + (ax * (c[3] + c[4]) - b6 * c[8]);
@@ -152,6 +162,7 @@ struct VC13Pre {
 };
 template <class T, class CV>
 __device__ __forceinline__ VC13Pre<T> vc13_prep(const CV& c, const double* p, bool with_w) {
+#pragma clang fp contract(off)
     const T k43 = (T)(p[0] * (4.0 / 3.0)), k12 = (T)(p[0] / 12.0);
     VC13Pre<T> q;
     T dsum = T(0);
@@ -160,7 +171,7 @@ __device__ __forceinline__ VC13Pre<T> vc13_prep(const CV& c, const double* p, bo
         q.ap[d] = k43 * c[1 + 2 * d];
         q.am[d] = k43 * c[2 + 2 * d];
         q.b[d] = k12 * c[7 + d];
-        dsum = dsum + ((q.ap[d] + q.am[d]) - T(2) * q.b[d]);
+        dsum = fma(T(-2), q.b[d], dsum + (q.ap[d] + q.am[d]));
     }
     q.d = c[0] + dsum;
     q.w = with_w ? (T)p[1] / q.d : T(0);
@@ -168,16 +179,17 @@ __device__ __forceinline__ VC13Pre<T> vc13_prep(const CV& c, const double* p, bo
 }
 template <class T, class ST>
 __device__ __forceinline__ T vc13_Au_pre(const ST& st, const VC13Pre<T>& q) {
+#pragma clang fp contract(off)
     T s = q.ap[0] * st.xp[0][0];
-    s = s + q.am[0] * st.xm[0][0];
-    s = s - q.b[0] * (st.xp[0][1] + st.xm[0][1]);
-    s = s + q.ap[1] * st.yp[0][0];
-    s = s + q.am[1] * st.ym[0][0];
-    s = s - q.b[1] * (st.yp[0][1] + st.ym[0][1]);
-    s = s + q.ap[2] * st.zp[0][0];
-    s = s + q.am[2] * st.zm[0][0];
-    s = s - q.b[2] * (st.zp[0][1] + st.zm[0][1]);
-    return q.d * st.c[0] - s;
+    s = fma(q.am[0], st.xm[0][0], s);
+    s = fma(-q.b[0], st.xp[0][1] + st.xm[0][1], s);
+    s = fma(q.ap[1], st.yp[0][0], s);
+    s = fma(q.am[1], st.ym[0][0], s);
+    s = fma(-q.b[1], st.yp[0][1] + st.ym[0][1], s);
+    s = fma(q.ap[2], st.zp[0][0], s);
+    s = fma(q.am[2], st.zm[0][0], s);
+    s = fma(-q.b[2], st.zp[0][1] + st.zm[0][1], s);
+    return fma(q.d, st.c[0], -s);
 }
 
 // v_f = A u_f for F fields sharing the coefficients.  p[0] = kappa.
@@ -189,17 +201,20 @@ struct OpVC13Apply {
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply_one(int, const ST& st, const AV&, const BV& c,
                                                      const double* p, T& o, double& rv, int) {
+#pragma clang fp contract(off)
         o = vc13_Au<T>(st, 0, c, (T)p[0]);
         rv = (double)o;
     }
     using Pre = VC13Pre<T>;
     template <class BV>
     __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+#pragma clang fp contract(off)
         return vc13_prep<T>(c, p, false);
     }
     template <class ST, class AV>
     __device__ __forceinline__ static void apply_pre(int, const ST& st, const AV&, const Pre& q,
                                                      const double*, T& o, double& rv, int) {
+#pragma clang fp contract(off)
         o = vc13_Au_pre<T>(st, q);
         rv = (double)o;
     }
@@ -215,6 +230,7 @@ struct OpVC13Jacobi {
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply_one(int f, const ST& st, const AV& gv, const BV& c,
                                                      const double* p, T& o, double& rv, int operand) {
+#pragma clang fp contract(off)
         const T kappa = (T)p[0], omega = (T)p[1];
         const T w = omega / vc13_diag<T>(c, kappa);
         const T r = gv[f] - vc13_Au<T>(st, 0, c, kappa);
@@ -224,13 +240,15 @@ struct OpVC13Jacobi {
     using Pre = VC13Pre<T>;
     template <class BV>
     __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+#pragma clang fp contract(off)
         return vc13_prep<T>(c, p, true);
     }
     template <class ST, class AV>
     __device__ __forceinline__ static void apply_pre(int f, const ST& st, const AV& gv, const Pre& q,
                                                      const double*, T& o, double& rv, int operand) {
+#pragma clang fp contract(off)
         const T r = gv[f] - vc13_Au_pre<T>(st, q);
-        o = st.c[0] + q.w * r;
+        o = fma(q.w, r, st.c[0]);
         rv = operand == RV_RESIDUAL ? (double)r : (double)(o - st.c[0]);
     }
 };
@@ -245,17 +263,20 @@ struct OpVC13Resid {
     template <class ST, class AV, class BV>
     __device__ __forceinline__ static void apply_one(int f, const ST& st, const AV& bv, const BV& c,
                                                      const double* p, double& o, double& rv, int) {
+#pragma clang fp contract(off)
         o = bv[f] - vc13_Au<double>(st, 0, c, p[0]);
         rv = o;
     }
     using Pre = VC13Pre<double>;
     template <class BV>
     __device__ __forceinline__ static Pre prep(const BV& c, const double* p) {
+#pragma clang fp contract(off)
         return vc13_prep<double>(c, p, false);
     }
     template <class ST, class AV>
     __device__ __forceinline__ static void apply_pre(int f, const ST& st, const AV& bv, const Pre& q,
                                                      const double*, double& o, double& rv, int) {
+#pragma clang fp contract(off)
         o = bv[f] - vc13_Au_pre<double>(st, q);
         rv = o;
     }

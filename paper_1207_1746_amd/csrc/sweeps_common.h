@@ -3,7 +3,6 @@
 #include <algorithm>
 #include "launch.h"
 #include "ops.h"
-#include "ring13.h"
 #include "zq13.h"
 
 namespace gk {
@@ -44,25 +43,6 @@ static hipError_t run7(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int*
     return hipErrorInvalidValue;
 }
 
-template <class Op, int V>
-static hipError_t run_ring(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nblocks) {
-    a.ntx = (a.g.nx + 64 * V - 1) / (64 * V);
-    a.nty = (a.g.ny + 3) / 4;
-    a.cz = c.cz;
-    a.ncz = (a.g.nz + c.cz - 1) / c.cz;
-    const int n = a.ntx * a.nty * a.ncz;
-    *nblocks = n;
-    if (n == 0) return hipSuccess;
-    if (red) {
-        hipLaunchKernelGGL((ring13_sweep<Op, V, true>), dim3(n), dim3(256), 0, s, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_reduce_finish(a.ra, n, s);
-    }
-    hipLaunchKernelGGL((ring13_sweep<Op, V, false>), dim3(n), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
 template <class Op, int V, int NW>
 static hipError_t run_zq(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nblocks) {
     a.ntx = (a.g.nx + 64 * V - 1) / (64 * V);
@@ -84,24 +64,21 @@ static hipError_t run_zq(TArgs& a, const TileCfg& c, bool red, hipStream_t s, in
 
 // (V, NW) shapes instantiated for the 13-point family (radius 2).  Several
 // fields: the z-queue driver, which addresses grids with 32-bit byte offsets
-// (V = 2 only with a 4-byte compute type); grids of 4 GiB or more take the
-// LDS-ring driver.  One field: the register-queue driver.
+// (V = 2 only with a 4-byte compute type; the host rejects grids of 4 GiB or
+// more for it).  One field: the register-queue driver.
 template <class Op>
 static hipError_t run13(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
     if constexpr (Op::NF > 1) {
         constexpr uint64_t es = std::max({sizeof(typename Op::SN), sizeof(typename Op::SA),
                                           sizeof(typename Op::SB), sizeof(typename Op::SO)});
-        const uint64_t span = (uint64_t)a.g.pz * (uint64_t)std::max(a.g.nz, 1) * es;
-        if (span >= ((uint64_t)1 << 32)) {
-            if constexpr (sizeof(typename Op::SN) <= 2) {
-                if (c.V == 2) return run_ring<Op, 2>(a, c, red, s, nb);
-            }
-            return run_ring<Op, 1>(a, c, red, s, nb);
-        }
+        if ((uint64_t)a.g.pz * (uint64_t)std::max(a.g.nz, 1) * es >= ((uint64_t)1 << 32))
+            return hipErrorInvalidValue;
         if (c.V == 1 && c.NW == 4) return run_zq<Op, 1, 4>(a, c, red, s, nb);
+        if (c.V == 1 && c.NW == 6) return run_zq<Op, 1, 6>(a, c, red, s, nb);
         if (c.V == 1 && c.NW == 8) return run_zq<Op, 1, 8>(a, c, red, s, nb);
         if constexpr (sizeof(typename Op::T) == 4) {
             if (c.V == 2 && c.NW == 4) return run_zq<Op, 2, 4>(a, c, red, s, nb);
+            if (c.V == 2 && c.NW == 6) return run_zq<Op, 2, 6>(a, c, red, s, nb);
             if (c.V == 2 && c.NW == 8) return run_zq<Op, 2, 8>(a, c, red, s, nb);
         }
         return hipErrorInvalidValue;

@@ -99,48 +99,57 @@ __device__ __forceinline__ R* at32(void* base, uint32_t e, uint32_t esize) {
     return reinterpret_cast<R*>(static_cast<char*>(base) + e * esize);
 }
 
-// V raw storage values of row (y, z) from column gx, boundary-synthesized
-// where any element lies outside the interior.  The row is the same for the
-// whole wave, so its boundary handling is a scalar branch; only the column
-// varies per lane.  Out-of-range columns read an in-range element (wrapped,
-// or clamped under the Dirichlet rule and then replaced by the boundary
-// value), so every access stays inside the grid.
-template <class S, int V>
-__device__ __forceinline__ RawV<S, V> load_raw(const void* base, const Geo& g, int gx, int y, int z,
-                                               RawE<S> bcs) {
-    const bool row_in = (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
-    RawE<S> e[V];
-    if (!row_in && g.bc == BC_DIRICHLET) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) e[i] = bcs;
-        return pack_elems<S, V>(e);
-    }
-    const int yy = row_in ? y : wrap_idx(y, g.ny, g.bc);
-    const int zz = row_in ? z : wrap_idx(z, g.nz, g.bc);
-    const uint32_t row = (uint32_t)zz * (uint32_t)g.pz + (uint32_t)yy * (uint32_t)g.py;
-    if (gx >= 0 && gx + V <= g.nx) return *at32<RawV<S, V>>(base, row + (uint32_t)gx, sizeof(S));
+// Column sources of one lane, fixed for the whole z march.  `x` is where the
+// lane's V-element vector is read when all V columns lie inside the interior
+// (`fast`); otherwise each element reads column xi[i] (wrapped, or clamped
+// and then replaced by the boundary value where xv[i] is false).  Every index
+// is inside the row, so every access stays inside the grid.
+template <int V>
+struct ColSrc {
+    int x;
+    bool fast;
+    int xi[V];
+    bool xv[V];
+};
+
+template <int V>
+__device__ __forceinline__ ColSrc<V> col_src(const Geo& g, int gx) {
+    ColSrc<V> c;
+    c.fast = gx >= 0 && gx + V <= g.nx;
+    c.x = c.fast ? gx : 0;
     const int xbc = g.bc == BC_DIRICHLET ? BC_CLAMP : g.bc;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         const int x = gx + i;
         const bool in = (unsigned)x < (unsigned)g.nx;
-        const RawE<S> val = *at32<RawE<S>>(base, row + (uint32_t)(in ? x : wrap_idx(x, g.nx, xbc)), sizeof(S));
-        e[i] = (in || g.bc != BC_DIRICHLET) ? val : bcs;
+        c.xi[i] = in ? x : wrap_idx(x, g.nx, xbc);
+        c.xv[i] = in || g.bc != BC_DIRICHLET;
     }
-    return pack_elems<S, V>(e);
+    return c;
 }
 
-// Pointwise row segment, streamed (read once per sweep).  Only points inside
-// the interior are meaningful; rows are padded to 16 elements, so a segment
-// starting inside the row stays inside the allocation.
-template <class S, int V>
-__device__ __forceinline__ RawV<S, V> load_pw_raw(const void* base, const Geo& g, int gx, int y, int z) {
-    RawV<S, V> r{};
-    if ((unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz && gx < g.nx) {
-        const uint32_t row = (uint32_t)z * (uint32_t)g.pz + (uint32_t)y * (uint32_t)g.py;
-        r = __builtin_nontemporal_load(at32<RawV<S, V>>(base, row + (uint32_t)gx, sizeof(S)));
+// Row segment of every field at element offset `row` (start of a row inside
+// the grid) through the lane's column sources.  Lanes whose columns are not
+// all inside the interior take one divergent branch for all fields.
+template <class S, int V, int NF>
+__device__ __forceinline__ void load_rows(const void* const* base, uint32_t row, const ColSrc<V>& c,
+                                          RawE<S> bcs, RawV<S, V> (&dst)[NF]) {
+    static_for<NF>([&](auto fi) __attribute__((always_inline)) {
+        constexpr int f = decltype(fi)::value;
+        dst[f] = *at32<RawV<S, V>>(base[f], row + (uint32_t)c.x, sizeof(S));
+    });
+    if (!c.fast) {
+        static_for<NF>([&](auto fi) __attribute__((always_inline)) {
+            constexpr int f = decltype(fi)::value;
+            RawE<S> e[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const RawE<S> val = *at32<RawE<S>>(base[f], row + (uint32_t)c.xi[i], sizeof(S));
+                e[i] = c.xv[i] ? val : bcs;
+            }
+            dst[f] = pack_elems<S, V>(e);
+        });
     }
-    return r;
 }
 
 template <class Op, int V, int NW, bool RED>
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(64 * NW) void zq13_sweep(TArgs a) {
     using SA = typename Op::SA;
     using SB = typename Op::SB;
     using SO = typename Op::SO;
-    constexpr int NF = Op::NF, NR = Op::NR, R = 2, QD = 5;
+    constexpr int NF = Op::NF, NR = Op::NR, R = 2;
     constexpr int NA = AtLeast1<Op::NA>::v, NB = AtLeast1<Op::NB>::v;
     constexpr int TX = 64 * V;
     // core columns start at a 16-byte boundary; R halo columns on each side
@@ -180,80 +189,126 @@ __global__ __launch_bounds__(64 * NW) void zq13_sweep(TArgs a) {
     const int hrow = (w < R) ? w : (NW + w);
     const int ccol = CO + lane * V;
     const RawE<SN> bcs = __builtin_bit_cast(RawE<SN>, Store<SN>::cv(g.bcv));
+    const bool dir = g.bc == BC_DIRICHLET;
+    const uint32_t pz = (uint32_t)g.pz, py = (uint32_t)g.py;
 
-    // x halo: lane 0 holds the R cells left of the tile, lane 63 the R cells
-    // right of it (one code path, so the values stay in registers)
+    // rows (wave-uniform): the core row and the y-halo row this wave stages
+    const bool yc_in = (unsigned)gy < (unsigned)g.ny, yh_in = (unsigned)hy < (unsigned)g.ny;
+    const uint32_t yc_off = (uint32_t)(yc_in ? gy : wrap_idx(gy, g.ny, dir ? BC_CLAMP : g.bc)) * py;
+    const uint32_t yh_off = (uint32_t)(yh_in ? hy : wrap_idx(hy, g.ny, dir ? BC_CLAMP : g.bc)) * py;
+    const bool yc_ok = yc_in || !dir, yh_ok = yh_in || !dir;
+    // pointwise grids: rows past the interior read a valid row (results unused)
+    const uint32_t ypw_off = (uint32_t)min(gy, g.ny - 1) * py;
+    const uint32_t xpw = gx < g.nx ? (uint32_t)gx : 0u;
+    // columns (per lane): the core vector and, on lanes 0 and 63, the x halo
+    const ColSrc<V> cc = col_src<V>(g, gx);
     const bool xh_lane = lane == 0 || lane == 63;
-    const int xh_x = lane == 0 ? x0 - R : x0 + TX;
+    const ColSrc<R> ch = col_src<R>(g, lane == 0 ? x0 - R : x0 + TX);
     const int xh_col = lane == 0 ? CO - R : CO + TX;
 
-    T q[NF][QD - 1][V];   // planes z-2 .. z+1, compute type
-    RN q4[NF], qn[NF];    // planes z+2 and z+3 (the latter in flight)
-    RN yh[NF];            // y-halo row of the next plane to stage
-    RX xh[NF];            // x-halo cells of the next plane to stage
-    RA pa[NA], pan[NA];   // pointwise grids of planes z and z+1
-    RB pb[NB], pbn[NB];
-
-    auto load_halo = [&](int z, RN (&yo)[NF], RX (&xo)[NF]) __attribute__((always_inline)) {
-        static_for<NF>([&](auto fi) __attribute__((always_inline)) {
-            constexpr int f = decltype(fi)::value;
-            if (has_halo_row) yo[f] = load_raw<SN, V>(a.nb[f], g, gx, hy, z, bcs);
-            if (xh_lane) xo[f] = load_raw<SN, R>(a.nb[f], g, xh_x, gy, z, bcs);
-        });
+    // plane z (wave-uniform): element offset of its first row, and whether it
+    // is inside the interior (planes outside read a valid plane; under the
+    // Dirichlet rule their values are then replaced by the boundary value)
+    auto zsrc = [&](int z, bool& ok) __attribute__((always_inline)) -> uint32_t {
+        const bool in = (unsigned)z < (unsigned)g.nz;
+        ok = in || !dir;
+        return (uint32_t)(in ? z : wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc)) * pz;
+    };
+    auto load_core = [&](int z, RN (&dst)[NF]) __attribute__((always_inline)) {
+        bool zok;
+        const uint32_t zo = zsrc(z, zok);
+        load_rows<SN, V, NF>(a.nb, zo + yc_off, cc, bcs, dst);
+        if (!(zok && yc_ok)) {
+            RawE<SN> e[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) e[i] = bcs;
+            static_for<NF>([&](auto fi) __attribute__((always_inline)) { dst[decltype(fi)::value] = pack_elems<SN, V>(e); });
+        }
+    };
+    RN yh[NF];   // y-halo row of the next plane to stage
+    RX xh[NF];   // x-halo cells of the next plane to stage
+    auto load_halo = [&](int z) __attribute__((always_inline)) {
+        bool zok;
+        const uint32_t zo = zsrc(z, zok);
+        if (has_halo_row) {
+            load_rows<SN, V, NF>(a.nb, zo + yh_off, cc, bcs, yh);
+            if (!(zok && yh_ok)) {
+                RawE<SN> e[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) e[i] = bcs;
+                static_for<NF>([&](auto fi) __attribute__((always_inline)) { yh[decltype(fi)::value] = pack_elems<SN, V>(e); });
+            }
+        }
+        if (xh_lane) {
+            load_rows<SN, R, NF>(a.nb, zo + yc_off, ch, bcs, xh);
+            if (!(zok && yc_ok)) {
+                RawE<SN> e[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) e[i] = bcs;
+                static_for<NF>([&](auto fi) __attribute__((always_inline)) { xh[decltype(fi)::value] = pack_elems<SN, R>(e); });
+            }
+        }
     };
     auto load_point = [&](int z, RA (&ao)[NA], RB (&bo)[NB]) __attribute__((always_inline)) {
+        const uint32_t e = (uint32_t)z * pz + ypw_off + xpw;
 #pragma unroll
-        for (int i = 0; i < Op::NA; ++i) ao[i] = load_pw_raw<SA, V>(a.pa[i], g, gx, gy, z);
+        for (int i = 0; i < Op::NA; ++i)
+            ao[i] = __builtin_nontemporal_load(at32<RA>(a.pa[i], e, sizeof(SA)));
 #pragma unroll
-        for (int i = 0; i < Op::NB; ++i) bo[i] = load_pw_raw<SB, V>(a.pb[i], g, gx, gy, z);
+        for (int i = 0; i < Op::NB; ++i)
+            bo[i] = __builtin_nontemporal_load(at32<RB>(a.pb[i], e, sizeof(SB)));
     };
 
-    // warm-up: planes z0-2 .. z0+2, the halo and the pointwise values of z0
+    // state at the start of step z: q = planes z-2 .. z+1 (compute type),
+    // r2[P] = plane z+2 and pw*[P] = pointwise values of plane z (storage
+    // type), yh / xh = halo of plane z.  Step z refills r2[1-P] and pw*[1-P]
+    // for step z+1, so consecutive steps swap buffers instead of copying.
+    T q[NF][4][V];
+    RN r2[2][NF];
+    RA pwa[2][NA];
+    RB pwb[2][NB];
+
 #pragma unroll
-    for (int s = 0; s < QD - 1; ++s) {
+    for (int s = 0; s < 4; ++s) {
+        RN raw[NF];
+        load_core(z0 - R + s, raw);
         static_for<NF>([&](auto fi) __attribute__((always_inline)) {
             constexpr int f = decltype(fi)::value;
-            const RN r = load_raw<SN, V>(a.nb[f], g, gx, gy, z0 - R + s, bcs);
 #pragma unroll
-            for (int v = 0; v < V; ++v) q[f][s][v] = unpack<T, SN, V>(r, v);
+            for (int v = 0; v < V; ++v) q[f][s][v] = unpack<T, SN, V>(raw[f], v);
         });
     }
-    static_for<NF>([&](auto fi) __attribute__((always_inline)) {
-        constexpr int f = decltype(fi)::value;
-        q4[f] = load_raw<SN, V>(a.nb[f], g, gx, gy, z0 + R, bcs);
-    });
-    load_halo(z0, yh, xh);
-    load_point(z0, pa, pb);
+    load_core(z0 + R, r2[0]);
+    load_halo(z0);
+    load_point(z0, pwa[0], pwb[0]);
 
     const bool row_ok = gy < g.ny;
     double acc = 0.0;
-    int buf = 0;
-    for (int z = z0; z < z1; ++z) {
+
+    auto step = [&](auto pc, int z) __attribute__((always_inline)) {
+        constexpr int P = decltype(pc)::value;
         const bool more = z + 1 < z1;
         if (more) {
-            static_for<NF>([&](auto fi) __attribute__((always_inline)) {
-                constexpr int f = decltype(fi)::value;
-                qn[f] = load_raw<SN, V>(a.nb[f], g, gx, gy, z + R + 1, bcs);
-            });
-            load_point(z + 1, pan, pbn);
+            load_core(z + R + 1, r2[1 - P]);
+            load_point(z + 1, pwa[1 - P], pwb[1 - P]);
         }
         // stage plane z: core row, x halo (edge lanes), y halo row
         static_for<NF>([&](auto fi) __attribute__((always_inline)) {
             constexpr int f = decltype(fi)::value;
 #pragma unroll
-            for (int v = 0; v < V; ++v) lds[buf][f][R + w][ccol + v] = q[f][R][v];
+            for (int v = 0; v < V; ++v) lds[P][f][R + w][ccol + v] = q[f][R][v];
             if (xh_lane) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[buf][f][R + w][xh_col + r] = unpack<T, SN, R>(xh[f], r);
+                for (int r = 0; r < R; ++r) lds[P][f][R + w][xh_col + r] = unpack<T, SN, R>(xh[f], r);
             }
             if (has_halo_row) {
 #pragma unroll
-                for (int v = 0; v < V; ++v) lds[buf][f][hrow][ccol + v] = unpack<T, SN, V>(yh[f], v);
+                for (int v = 0; v < V; ++v) lds[P][f][hrow][ccol + v] = unpack<T, SN, V>(yh[f], v);
             }
         });
         __syncthreads();
         // the staged halo registers are free again: fetch the next plane's
-        if (more) load_halo(z + 1, yh, xh);
+        if (more) load_halo(z + 1);
 
         T res[NF][V];
         double redv[NR][V];
@@ -261,31 +316,32 @@ __global__ __launch_bounds__(64 * NW) void zq13_sweep(TArgs a) {
         for (int v = 0; v < V; ++v) {
             T av[NA], bv[NB];
 #pragma unroll
-            for (int i = 0; i < NA; ++i) av[i] = Op::NA > 0 ? unpack<T, SA, V>(pa[i], v) : T(0);
+            for (int i = 0; i < NA; ++i) av[i] = Op::NA > 0 ? unpack<T, SA, V>(pwa[P][i], v) : T(0);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) bv[i] = Op::NB > 0 ? unpack<T, SB, V>(pb[i], v) : T(0);
+            for (int i = 0; i < NB; ++i) bv[i] = Op::NB > 0 ? unpack<T, SB, V>(pwb[P][i], v) : T(0);
             const typename Op::Pre pre = Op::prep(bv, a.p);
             static_for<NF>([&](auto fi) __attribute__((always_inline)) {
                 constexpr int f = decltype(fi)::value;
-                const T(&row)[LW] = lds[buf][f][R + w];
+                const T(&row)[LW] = lds[P][f][R + w];
                 Star<T, 1, R> st;
                 st.c[0] = q[f][R][v];
 #pragma unroll
                 for (int r = 1; r <= R; ++r) {
                     st.xm[0][r - 1] = (v - r >= 0) ? q[f][R][(v - r) >= 0 ? v - r : 0] : row[ccol + v - r];
                     st.xp[0][r - 1] = (v + r < V) ? q[f][R][(v + r) < V ? v + r : 0] : row[ccol + v + r];
-                    st.ym[0][r - 1] = lds[buf][f][R + w - r][ccol + v];
-                    st.yp[0][r - 1] = lds[buf][f][R + w + r][ccol + v];
+                    st.ym[0][r - 1] = lds[P][f][R + w - r][ccol + v];
+                    st.yp[0][r - 1] = lds[P][f][R + w + r][ccol + v];
                     st.zm[0][r - 1] = q[f][R - r][v];
-                    st.zp[0][r - 1] = r == 1 ? q[f][R + 1][v] : unpack<T, SN, V>(q4[f], v);
                 }
+                st.zp[0][0] = q[f][R + 1][v];
+                st.zp[0][1] = unpack<T, SN, V>(r2[P][f], v);
                 double rv1;
                 Op::apply_pre(f, st, av, pre, a.p, res[f][v], rv1, a.operand);
                 redv[f][v] = rv1;
             });
         }
         if (row_ok) {
-            const uint32_t rowoff = (uint32_t)z * (uint32_t)g.pz + (uint32_t)gy * (uint32_t)g.py;
+            const uint32_t rowoff = (uint32_t)z * pz + (uint32_t)gy * py;
             if (gx + V <= g.nx) {
                 static_for<NF>([&](auto fi) __attribute__((always_inline)) {
                     constexpr int f = decltype(fi)::value;
@@ -321,19 +377,19 @@ __global__ __launch_bounds__(64 * NW) void zq13_sweep(TArgs a) {
             static_for<NF>([&](auto fi) __attribute__((always_inline)) {
                 constexpr int f = decltype(fi)::value;
 #pragma unroll
-                for (int s = 0; s + 2 < QD; ++s)
+                for (int s = 0; s < 3; ++s)
 #pragma unroll
                     for (int v = 0; v < V; ++v) q[f][s][v] = q[f][s + 1][v];
 #pragma unroll
-                for (int v = 0; v < V; ++v) q[f][QD - 2][v] = unpack<T, SN, V>(q4[f], v);
-                q4[f] = qn[f];
+                for (int v = 0; v < V; ++v) q[f][3][v] = unpack<T, SN, V>(r2[P][f], v);
             });
-#pragma unroll
-            for (int i = 0; i < NA; ++i) pa[i] = pan[i];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) pb[i] = pbn[i];
         }
-        buf ^= 1;
+    };
+
+    for (int z = z0; z < z1; z += 2) {
+        step(std::integral_constant<int, 0>{}, z);
+        if (z + 1 >= z1) break;
+        step(std::integral_constant<int, 1>{}, z + 1);
     }
     if (RED) block_reduce(acc, a.ra, tile);
 }

@@ -101,3 +101,21 @@ def test_graph_capture_replays_match_eager(sctx):
         ctx.do_all(G.K_LINEAR, [a], [tmp], terms=[(0, 0, 0, 0, 0, 1.0, -1)])
         torch.cuda.synchronize()
     graph.close()
+
+
+def test_vc13_five_fields_refuse_grids_of_4_gib(ctx):
+    """The five-field 13-point kernels address grids with 32-bit byte offsets:
+    a grid of 4 GiB or more is refused on the host, before any launch.  The
+    FP64 residual kind has the smallest footprint for a 4 GiB grid (FP64 x and
+    b, BF16 coefficients, F32 outputs: about 65 GB, left uninitialized)."""
+    import torch
+    shape = (513, 1024, 1024)  # 4.3 GB per FP64 grid
+    x = [ctx.grid(shape, G.F64, halo=2) for _ in range(5)]
+    b = [ctx.grid(shape, G.F64, halo=0) for _ in range(5)]
+    c = [ctx.grid(shape, G.BF16, halo=0) for _ in range(10)]
+    r = [ctx.grid(shape, G.F32, halo=0) for _ in range(5)]
+    assert x[0].storage.numel() * 8 >= 1 << 32
+    assert _err(lambda: ctx.do_all(G.K_VC13_RESID, x + b + c, r, p=(0.25, 0.0, 5))) == G.ERR_UNSUPPORTED
+    del x, b, c, r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()

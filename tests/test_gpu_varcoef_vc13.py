@@ -143,3 +143,42 @@ def test_vc13_jacobi_and_resid(ctx, dt):
         tot += oracle.sumsq(r)
         np.testing.assert_allclose(gr[f].numpy(), r, rtol=U32 * 2, atol=1e-12 * np.abs(r).max())
     assert abs(ss - tot) <= 1e-12 * tot
+
+
+@pytest.mark.parametrize("dt", [G.BF16, G.F32, G.F64])
+@pytest.mark.parametrize("bc", [G.DIRICHLET, G.PERIODIC, G.CLAMP])
+def test_vc13_five_field_tiling_invariance(ctx, dt, bc):
+    """do_all outputs of the five-field 13-point kinds are bitwise identical
+    for every tile shape (ragged in x, y and z), under every boundary rule;
+    the Dirichlet case with a non-zero boundary value also matches the oracle."""
+    shape = (11, 13, 150)
+    nf = 5
+    c, b = W.vc13_grids(shape[2], shape[1], shape[0], nf)
+    fields = W.vc13_fields(shape[2], shape[1], shape[0], nf)
+    bcv = 0.5 if bc == G.DIRICHLET else 0.0
+    gf = [ctx.grid(shape, dt, halo=2, bc=bc, bc_value=bcv, data=f) for f in fields]
+    gc = [ctx.grid(shape, dt, halo=0, data=x) for x in c]
+    gg = [ctx.grid(shape, dt, halo=0, data=x) for x in b]
+    shapes = [(1, 4, 16), (1, 6, 3), (1, 8, 1)]
+    if dt != G.F64:
+        shapes += [(2, 4, 3), (2, 6, 16), (2, 8, 1)]
+    for kind, ins, p in ((G.K_VC13_APPLY, gf + gc, (W.VC13_KAPPA, 0.0, nf)),
+                         (G.K_VC13_JACOBI, gf + gg + gc, (W.VC13_KAPPA, 6 / 7, nf))):
+        ref = None
+        for t in shapes:
+            ctx.tile_set(kind, gf[0], t)
+            go = [ctx.grid(shape, dt, halo=2) for _ in range(nf)]
+            ctx.do_all(kind, ins, go, p=p)
+            got = np.stack([o.view.double().cpu().numpy() for o in go])
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (kind, t)
+        ctx.tile_clear()
+        if bc == G.DIRICHLET and kind == G.K_VC13_APPLY:
+            us = {G.F64: 1e-16, G.F32: U32, G.BF16: 2.0 ** -8}[dt]
+            for f in range(nf):
+                stored = gf[f].view.double().cpu().numpy()
+                ex = oracle.vc13_apply(stored, c, W.VC13_KAPPA, bcv=bcv)
+                terms = 1.5 * max(np.abs(stored).max(), bcv) * (1 + W.VC13_KAPPA * 3 * (4 / 3 * 2 * 2 + 4 / 12))
+                tol = 4 * us * max(np.abs(ex).max(), 1.0) + 64 * (U32 if dt != G.F64 else 1e-16) * terms
+                assert np.abs(ref[f] - ex).max() <= tol, f
