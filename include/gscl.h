@@ -134,7 +134,15 @@ typedef struct gscl_batch gscl_batch;
  *   Fused operands: RESIDUAL (r in F64).
  * GSCL_K_POISSON_RESID: in = {x (F64), f (F64)}, out = {r (F32)}:
  *   r = f - (S - 6 x)/h^2 computed in F64, stored F32 (ndim 3); p[1] = h^2.
- *   Fused operand RESIDUAL = r (F64).                                       */
+ *   Fused operand RESIDUAL = r (F64).
+ * GSCL_K_WJACOBI_TB (Section 2: wide ghost areas, time loops over a
+ *   stencil): k successive GSCL_K_WJACOBI sweeps in one pass over memory.
+ *   in = {u} or {u, f}; out = {u after k sweeps}, which may not overlap u or
+ *   f; p[0] = omega, p[1] = h^2, p[2] = k in 1..4.  ndim 3, F64 or F32,
+ *   Dirichlet or periodic rule (CLAMP: GSCL_ERR_UNSUPPORTED).  The result is
+ *   bitwise the one k separate WJACOBI sweeps give; fused operands refer to
+ *   the last sweep (UPDATE = u_k - u_{k-1}, RESIDUAL of u_{k-1}).  Its tile
+ *   uses only cz (output planes per block).                                 */
 enum {
     GSCL_K_LINEAR = 0,
     GSCL_K_WJACOBI = 1,
@@ -143,7 +151,8 @@ enum {
     GSCL_K_VC13_APPLY = 4,
     GSCL_K_VC13_JACOBI = 5,
     GSCL_K_VC13_RESID = 6,
-    GSCL_K_POISSON_RESID = 7
+    GSCL_K_POISSON_RESID = 7,
+    GSCL_K_WJACOBI_TB = 8
 };
 
 typedef struct {
@@ -231,7 +240,9 @@ int gscl_do_reduce(gscl_ctx *ctx, const gscl_reduce_desc *rd, const gscl_grid *a
  * (kind, dtype, extents) key of a context.  V in {1,2,4} (radius-2 kinds
  * {1,2} with FP32 math, 1 with FP64 math; F64 {1,2}), NW in {4,8} (radius-2
  * kinds: 4 for one field, {4,6,8} for five fields), cz >= 1.  A shape with no
- * kernel for the kind is reported by the launch as GSCL_ERR_UNSUPPORTED. */
+ * kernel for the kind is reported by the launch as GSCL_ERR_UNSUPPORTED.
+ * GSCL_K_WJACOBI_TB has a fixed block shape (V = 1, NW = 16, two rows per
+ * wave): gscl_tile_set takes only its cz and gscl_tile_get reports it so. */
 typedef struct { int32_t V, NW, cz; } gscl_tile;
 int gscl_tile_get(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, gscl_tile *out);
 int gscl_tile_set(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, const gscl_tile *tile);

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "api_internal.h"
+#include "tb7.h"
 
 static thread_local std::string g_last_error;
 
@@ -209,6 +210,20 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
     if (it != c->tiles.end()) return it->second;
     gk::TileCfg t;
     const int64_t nx = d.n[0];
+    if (kind == GSCL_K_WJACOBI_TB) {
+        // output planes per block (measured on MI355X from 64^3 to 512^3): the
+        // largest power of two up to (output tiles per plane) * nz / 160,
+        // within 1..64 -- long enough to amortize the 2k warm-up planes, short
+        // enough for about one block per CU on mid-size grids
+        const int64_t cols = ((nx + 55) / 56) * ((d.n[1] + 23) / 24);
+        const int64_t want = std::max<int64_t>(1, cols * d.n[2] / 160);
+        int64_t cz = 1;
+        while (cz * 2 <= want && cz < 64) cz *= 2;
+        t.V = 1;
+        t.NW = gk::TB_NW;
+        t.cz = (int)std::max<int64_t>(1, std::min<int64_t>(cz, std::max<int64_t>(d.n[2], 1)));
+        return t;
+    }
     if (kind == GSCL_K_IMG_BOX5_LAP) {  // rows per block of the image kernel (measured best: 8)
         t.V = 4;
         t.NW = 4;
@@ -251,13 +266,17 @@ static gk::TileCfg reduce_tile(gk::TileCfg t, const gscl_grid_desc& d) {
 
 extern "C" int gscl_tile_set(gscl_ctx* c, int kind, const gscl_grid_desc* gd, const gscl_tile* t) {
     if (!ctx_ok(c) || !gd || !t) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
-    if (t->V != 1 && t->V != 2 && t->V != 4) return gscl_fail(GSCL_ERR_ARG, "V must be 1, 2 or 4");
-    if (t->NW != 4 && t->NW != 6 && t->NW != 8) return gscl_fail(GSCL_ERR_ARG, "NW must be 4, 6 or 8");
+    // the temporally blocked kind has a fixed block shape: only cz applies
+    const bool shape_fixed = kind == GSCL_K_WJACOBI_TB;
+    if (!shape_fixed && t->V != 1 && t->V != 2 && t->V != 4) return gscl_fail(GSCL_ERR_ARG, "V must be 1, 2 or 4");
+    if (!shape_fixed && t->NW != 4 && t->NW != 6 && t->NW != 8)
+        return gscl_fail(GSCL_ERR_ARG, "NW must be 4, 6 or 8");
     if (t->cz < 1) return gscl_fail(GSCL_ERR_ARG, "cz must be >= 1");
     gscl_grid_desc d = *gd;
     int rc = resolve_layout(&d);
     if (rc) return rc;
-    c->tiles[std::make_tuple(kind, d.dtype, d.n[0], d.n[1], d.n[2])] = gk::TileCfg{t->V, t->NW, t->cz};
+    c->tiles[std::make_tuple(kind, d.dtype, d.n[0], d.n[1], d.n[2])] =
+        shape_fixed ? gk::TileCfg{1, gk::TB_NW, t->cz} : gk::TileCfg{t->V, t->NW, t->cz};
     return GSCL_OK;
 }
 
@@ -470,6 +489,42 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
                 fill_red(c, fused, a.ra);
             }
             he = gk::launch_wjacobi(a, dt, g0->d.ndim, n_in == 2, t, red, c->stream, &nblocks);
+            break;
+        }
+        case GSCL_K_WJACOBI_TB: {
+            if (n_in < 1 || n_in > 2 || n_out != 1)
+                return gscl_fail(GSCL_ERR_ARG, "WJACOBI_TB takes {u[, f]} -> {u_k}");
+            if (dt != GSCL_F64 && dt != GSCL_F32) return gscl_fail(GSCL_ERR_DTYPE, "WJACOBI_TB needs F64 or F32 grids");
+            if ((rc = check_dtypes(in, 0, n_in, dt, "input")) || (rc = check_dtypes(out, 0, n_out, dt, "output")))
+                return rc;
+            if ((rc = check_nb(in, 0, 1, 1, out, n_out, 3))) return rc;
+            // f is read over the whole working region of a block, not only at
+            // the point being written: it may not overlap the output either
+            if (n_in == 2 && overlaps(in[1], out[0]))
+                return gscl_fail(GSCL_ERR_ALIAS, "WJACOBI_TB output aliases the right-hand side");
+            if (g0->d.bc == GSCL_BC_CLAMP)
+                return gscl_fail(GSCL_ERR_UNSUPPORTED, "WJACOBI_TB supports the Dirichlet and periodic rules");
+            if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "WJACOBI_TB needs h^2 != 0 in p[1]");
+            const double kd = op->p[2];
+            if (!(kd >= 1.0 && kd <= (double)gk::TB_KMAX) || kd != (double)(int)kd)
+                return gscl_fail(GSCL_ERR_ARG, "WJACOBI_TB needs k = p[2] in 1..%d", gk::TB_KMAX);
+            gk::TBArgs ta{};
+            ta.g = geo_of(g0);
+            ta.u = in[0]->ptr;
+            ta.f = n_in == 2 ? in[1]->ptr : nullptr;
+            ta.out = out[0]->ptr;
+            ta.p[0] = op->p[0];
+            ta.p[1] = op->p[1];
+            ta.p[2] = 1.0 / op->p[1];
+            ta.k = (int)kd;
+            ta.operand = red ? fused->operand : 0;
+            gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
+            ta.cz = t.cz;
+            if (red) {
+                if ((rc = ensure_partials(c, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
+                fill_red(c, fused, ta.ra);
+            }
+            he = gk::launch_wjacobi_tb(ta, dt == GSCL_F64 ? 0 : 1, n_in == 2, red, c->stream, &nblocks);
             break;
         }
         case GSCL_K_POISSON_RESID: {

@@ -1,0 +1,40 @@
+// Temporally blocked weighted-Jacobi instantiations (k sweeps per pass).
+#include "launch.h"
+#include "tb7.h"
+
+namespace gk {
+
+template <class T, bool HAS_F, int KMAX>
+static hipError_t run_tb(TBArgs& a, bool red, hipStream_t s, int* nblocks) {
+    const int ox = 64 - 2 * a.k, oy = TB_ROWS - 2 * a.k;
+    a.ntx = (a.g.nx + ox - 1) / ox;
+    a.nty = (a.g.ny + oy - 1) / oy;
+    a.ncz = (a.g.nz + a.cz - 1) / a.cz;
+    const int n = a.ntx * a.nty * a.ncz;
+    *nblocks = n;
+    if (n == 0) return hipSuccess;
+    if (red) {
+        hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, true>), dim3(n), dim3(64 * TB_NW), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_reduce_finish(a.ra, n, s);
+    }
+    hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, false>), dim3(n), dim3(64 * TB_NW), 0, s, a);
+    return hipGetLastError();
+}
+
+int tb_blocks(const Geo& g, int k, int cz) {
+    const int ox = 64 - 2 * k, oy = TB_ROWS - 2 * k;
+    return ((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * ((g.nz + cz - 1) / cz);
+}
+
+hipError_t launch_wjacobi_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nb) {
+    if (a.k < 1 || a.k > TB_KMAX) return hipErrorInvalidValue;
+    if (dtype == 0)
+        return has_f ? run_tb<double, true, TB_KMAX>(a, red, s, nb) : run_tb<double, false, TB_KMAX>(a, red, s, nb);
+    if (dtype == 1)
+        return has_f ? run_tb<float, true, TB_KMAX>(a, red, s, nb) : run_tb<float, false, TB_KMAX>(a, red, s, nb);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gk

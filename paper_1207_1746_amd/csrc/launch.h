@@ -31,6 +31,13 @@ hipError_t launch_vc13_resid(TArgs& a, int dtype_c, int nfields, const TileCfg& 
 // Blocks a tiled launch with this configuration would use.
 int tiled_blocks(const Geo& g, const TileCfg& c);
 
+// Weighted Jacobi, k sweeps per pass (temporal blocking), 3D, F64 (dtype 0)
+// or F32 (dtype 1), Dirichlet or periodic; k in 1..TB_KMAX.
+struct TBArgs;
+constexpr int TB_KMAX = 4;
+hipError_t launch_wjacobi_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nblocks);
+int tb_blocks(const Geo& g, int k, int cz);
+
 // Generic linear operator (any offsets, per-grid boundary rule).
 struct LinTerm {
     int out, grid, dx, dy, dz, coef;

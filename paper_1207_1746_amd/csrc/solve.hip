@@ -177,10 +177,27 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
         std::vector<gscl_grid*> w(nf);
         for (int f = 0; f < nf; ++f) w[f] = carve(c, xd, GSCL_F64, R, cur, cl.grids);
         const int S = sd->check_every;
-        // capture one chunk: x -> w -> x ... (S even ends in x)
+        // A chunk of S sweeps is a sequence of passes over memory.  Poisson
+        // chunks on large grids run temporally blocked passes of up to TB_KMAX
+        // sweeps (the same sweeps bit for bit, fewer passes); elsewhere every
+        // pass is one sweep.  The pass count is kept even so the chunk ends in x.
+        const bool tb = poisson && xd.n[0] * xd.n[1] * xd.n[2] >= (int64_t)144 * 144 * 144;
+        std::vector<int> passes;
+        if (tb) {
+            for (int left = S; left > 0; left -= passes.back()) passes.push_back(std::min(left, gk::TB_KMAX));
+            if (passes.size() % 2) {
+                const int last = passes.back();
+                passes.pop_back();
+                passes.push_back(last - last / 2);
+                passes.push_back(last / 2);
+            }
+        } else {
+            passes.assign(S, 1);
+        }
+        // capture one chunk: x -> w -> x ...
         if ((rc = gscl_graph_begin(c))) return rc;
-        for (int k = 1; k <= S && rc == GSCL_OK; ++k) {
-            const bool odd = k % 2 == 1;
+        for (size_t q = 0; q < passes.size() && rc == GSCL_OK; ++q) {
+            const bool odd = q % 2 == 0;
             std::vector<gscl_grid*> in, out;
             for (int f = 0; f < nf; ++f) {
                 in.push_back(odd ? x[f] : w[f]);
@@ -188,11 +205,12 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
             }
             gscl_stencil_desc op;
             memset(&op, 0, sizeof op);
-            const gscl_reduce_desc* red = k == S ? &chk : nullptr;
+            const gscl_reduce_desc* red = q + 1 == passes.size() ? &chk : nullptr;
             if (poisson) {
-                op.kind = GSCL_K_WJACOBI;
+                op.kind = passes[q] > 1 ? GSCL_K_WJACOBI_TB : GSCL_K_WJACOBI;
                 op.p[0] = sd->omega;
                 op.p[1] = sd->h2;
+                op.p[2] = passes[q];
                 in.push_back(const_cast<gscl_grid*>(b[0]));
                 rc = gscl_do_all(c, &op, in.data(), 2, out.data(), 1, red, nullptr);
             } else {

@@ -119,3 +119,20 @@ def test_batch_mixed_sizes_up_to_192(sctx):
         u, _, f = grids[i]
         _, _, res = oracle.wjacobi_sweep(u.numpy(), f, 6 / 7, r.h2)
         assert math.sqrt(oracle.sumsq(res) / oracle.sumsq(f)) <= 1e-8
+
+
+@pytest.mark.parametrize("n,S", [(150, 10), (150, 6), (160, 4)])
+def test_poisson_temporal_chunks_match_closed_form_trace(sctx, n, S):
+    """Grids of 144^3 points or more run their chunks as temporally blocked
+    passes (S = 10 -> 4+4+1+1, 6 -> 4+2, 4 -> 2+2): same stopping sweep as
+    the closed-form residual trace, and the oracle's residual of the answer."""
+    ctx = sctx
+    req = W.poisson_requests(count=1, qps=float("inf"), nmin=n, nmax=n, seed_index=n)[0]
+    _, f = W.poisson_fields(req)
+    expect = _predicted_stop(req, S, 1e-8)
+    u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+    st = ctx.solve(G.K_WJACOBI, [u], [gf], h2=req.h2, rtol=1e-8, check_every=S)
+    assert st["sweeps"] == expect
+    _, _, res = oracle.wjacobi_sweep(u.numpy(), f, 6 / 7, req.h2)
+    assert math.sqrt(oracle.sumsq(res) / oracle.sumsq(f)) <= 1e-8

@@ -1,0 +1,112 @@
+"""Temporal blocking (k weighted-Jacobi sweeps per pass, Section 2's wide ghost
+areas): the result must be the one k separate sweeps give, bit for bit, under
+every supported boundary rule, at ragged sizes that leave partial tiles in x,
+y and z; it is also checked against k applications of the oracle's sweep,
+with the fused reduction of the last sweep."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1207_1746_amd as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _plain(ctx, u, f, k, omega, h2, dt, bc, bcv):
+    shape = u.shape
+    a = ctx.grid(shape, dt, halo=1, bc=bc, bc_value=bcv, data=u)
+    b = ctx.grid(shape, dt, halo=1, bc=bc, bc_value=bcv)
+    ins_f = [ctx.grid(shape, dt, halo=0, data=f)] if f is not None else []
+    for _ in range(k):
+        ctx.do_all(G.K_WJACOBI, [a] + ins_f, [b], p=(omega, h2))
+        a, b = b, a
+    return a.view.clone()
+
+
+@pytest.mark.parametrize("dt", [G.F64, G.F32])
+@pytest.mark.parametrize("bc", [G.DIRICHLET, G.PERIODIC])
+@pytest.mark.parametrize("with_f", [False, True])
+def test_tb_equals_k_plain_sweeps_bitwise(ctx, dt, bc, with_f):
+    import torch
+    shape = (13, 37, 75)
+    g = np.random.default_rng(21)
+    u = g.standard_normal(shape)
+    f = g.standard_normal(shape) if with_f else None
+    omega, h2 = 0.8, 0.25
+    bcv = 0.5 if bc == G.DIRICHLET else 0.0
+    gu = ctx.grid(shape, dt, halo=1, bc=bc, bc_value=bcv, data=u)
+    gf = [ctx.grid(shape, dt, halo=0, data=f)] if with_f else []
+    for k in (1, 2, 3, 4):
+        ref = _plain(ctx, u, f, k, omega, h2, dt, bc, bcv)
+        for cz in (1, 3, 16):
+            ctx.tile_set(G.K_WJACOBI_TB, gu, (1, 16, cz))
+            go = ctx.grid(shape, dt, halo=1)
+            ctx.do_all(G.K_WJACOBI_TB, [gu] + gf, [go], p=(omega, h2, k))
+            assert torch.equal(go.view, ref), (k, cz)
+    ctx.tile_clear()
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_tb_matches_oracle_with_fused_reduction(ctx, k):
+    shape = (20, 30, 90)
+    g = np.random.default_rng(22)
+    u = g.standard_normal(shape)
+    f = g.standard_normal(shape)
+    omega, h2 = 6 / 7, 1.0 / 31 ** 2
+    gu = ctx.grid(shape, G.F64, halo=1, data=u)
+    gf = ctx.grid(shape, G.F64, halo=0, data=f)
+    go = ctx.grid(shape, G.F64, halo=1)
+    r_upd = ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [go], p=(omega, h2, k), reduce=(G.R_L2, G.RV_UPDATE))
+    r_res = ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [go], p=(omega, h2, k), reduce=(G.R_L2, G.RV_RESIDUAL))
+    x = u
+    for _ in range(k):
+        prev = x
+        x, upd, res = oracle.wjacobi_sweep(prev, f, omega, h2)
+    scale = np.abs(u).max() + h2 * np.abs(f).max()
+    np.testing.assert_allclose(go.numpy(), x, rtol=0, atol=1e-13 * scale * k)
+    assert abs(r_upd - np.sqrt(oracle.sumsq(upd))) <= 1e-11 * r_upd
+    assert abs(r_res - np.sqrt(oracle.sumsq(res))) <= 1e-11 * r_res
+
+
+def test_tb_errors(ctx):
+    shape = (6, 7, 40)
+    gu = ctx.grid(shape, G.F64, halo=1).fill(1.0)
+    gf = ctx.grid(shape, G.F64, halo=0).fill(0.0)
+    go = ctx.grid(shape, G.F64, halo=1)
+
+    def err(fn):
+        with pytest.raises(G.GsclError) as e:
+            fn()
+        return e.value.code
+
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [gu], [go], p=(1.0, 1.0, 5))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [gu], [go], p=(1.0, 1.0, 0))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [gf], p=(1.0, 1.0, 2))) == G.ERR_ALIAS
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [gu], [gu], p=(1.0, 1.0, 2))) == G.ERR_ALIAS
+    gc = ctx.grid(shape, G.F64, halo=1, bc=G.CLAMP).fill(1.0)
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [gc], [go], p=(1.0, 1.0, 2))) == G.ERR_UNSUPPORTED
+    g2 = ctx.grid((3, 7, 40), G.F64, halo=1, ndim=2)
+    h2 = ctx.grid((3, 7, 40), G.F64, halo=1, ndim=2)
+    assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [g2], [h2], p=(1.0, 1.0, 2))) == G.ERR_SHAPE
+
+
+def test_tb_full_size_512_f64_bitwise(ctx):
+    """512^3 FP64 with a right-hand side, default tile, k = 4 against 4 sweeps."""
+    import torch
+    n = 512
+    shape = (n, n, n)
+    gu = ctx.grid(shape, G.F64, halo=1)
+    gf = ctx.grid(shape, G.F64, halo=0)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    gu.view.copy_(torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen))
+    gf.view.copy_(torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen))
+    a = ctx.grid(shape, G.F64, halo=1)
+    b = ctx.grid(shape, G.F64, halo=1)
+    a.view.copy_(gu.view)
+    h2 = 1.0 / (n + 1) ** 2
+    for _ in range(4):
+        ctx.do_all(G.K_WJACOBI, [a, gf], [b], p=(6 / 7, h2))
+        a, b = b, a
+    go = ctx.grid(shape, G.F64, halo=1)
+    ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [go], p=(6 / 7, h2, 4))
+    assert torch.equal(go.view, a.view)
