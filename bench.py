@@ -38,6 +38,7 @@ KERNEL_SOURCES = {
                                      "k_sweep_wjacobi.hip")],
     "image_8192_u8": [_CS + f for f in ("kcommon.h", "k_image.hip")],
     "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
+    "wjacobi_tb_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "tb7.h", "k_sweep_tb.hip")],
     "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "zq13.h", "ops.h", "sweeps_common.h",
                                   "k_sweep_vc13a.hip")],
 }
@@ -205,6 +206,91 @@ class Jacobi:
         return {"value": round(self.units_per_step * reps / dt / 1e9, 4), "unit": self.unit,
                 "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"{reps} full runs of the workload in {dt:.1f} s"}
+
+
+class JacobiTB:
+    """Weighted Jacobi with a right-hand side on a 512^3 FP64 cube, Dirichlet
+    0: 16 sweeps per step as four temporally blocked passes of 4 sweeps (the
+    last with the fused L2 norm of its update).  The same 16 sweeps as plain
+    one-sweep passes are timed beside it; both give the same grid bit for bit."""
+    key = "wjacobi_tb_512"
+    bytes_per_point = 24  # per pass: u and f read once, the 4-sweep result written once
+
+    def __init__(self, ctx, n=512, sweeps=16, k=4):
+        import torch
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G = G
+        self.n, self.sweeps, self.k = n, sweeps, k
+        u0, self.h2 = W.jacobi_cube(n)
+        f = W.jacobi_rhs(n)
+        self.host = (u0, f)
+        self.a = ctx.grid(u0.shape, G.F64, halo=1, data=u0)
+        self.b = ctx.grid(u0.shape, G.F64, halo=1)
+        self.f = ctx.grid(u0.shape, G.F64, halo=0, data=f)
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        self.points = n ** 3
+        self.units_per_step = self.points * sweeps
+        self.unit = "Gpts/s"
+        self.extra = {}
+
+    def _run(self, kind, k, ev=None):
+        G = self.G
+        passes = self.sweeps // k
+        for q in range(passes):
+            src, dst = (self.a, self.b) if q % 2 == 0 else (self.b, self.a)
+            last = q == passes - 1
+            if ev is not None and not last:
+                ev.begin()
+            self.ctx.do_all(kind, [src, self.f], [dst], p=(6 / 7, self.h2, k),
+                            reduce=(G.R_L2, G.RV_UPDATE) if last else None,
+                            dev_result=self.res if last else None)
+            if ev is not None and not last:
+                ev.end()
+
+    def step(self, ev=None):
+        self._run(self.G.K_WJACOBI_TB, self.k, ev)
+
+    def after(self):
+        """The same sweeps as plain passes, and the per-sweep comparison."""
+        import torch
+        self._run(self.G.K_WJACOBI, 1)
+        sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            self._run(self.G.K_WJACOBI, 1)
+        b.record()
+        sync()
+        ms = a.elapsed_time(b) / reps
+        self.extra = {"plain_sweeps": {"ms_per_step": round(ms, 3),
+                                       "Gpts_s": round(self.units_per_step / ms / 1e6, 2),
+                                       "GBs": round(24 * self.units_per_step / ms / 1e6, 1)},
+                      "sweeps_per_pass": self.k,
+                      "note": "a pass reads u and f once and writes once for 4 sweeps"}
+
+    def config(self):
+        return {"workload": f"weighted Jacobi 7-point {self.n}^3 FP64 with right-hand side, Dirichlet 0, "
+                            f"{self.sweeps} sweeps per step as temporally blocked passes of {self.k} "
+                            f"+ L2 of the last update", "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        u0, f = self.host
+        t0 = time.perf_counter()
+        reps = 0
+        u = u0
+        while True:
+            u, _, _ = oracle.wjacobi_sweep(u, f, 6 / 7, self.h2)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} single FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
 
 
 class Image:
@@ -435,7 +521,8 @@ class VC13:
                 "sample": f"{reps} single-field FP64 applies in {dt:.1f} s (scaled to 5 fields)"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "image": Image, "serve": Serve, "reduce": Reduce,
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "image": Image, "serve": Serve,
+             "reduce": Reduce,
              "vc13": VC13}
 
 
@@ -556,7 +643,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"varcoef": "f32", "jacobi": "f64", "image": "u8", "reduce": "f64", "vc13": "bf16"}[args.config],
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "image": "u8", "reduce": "f64",
+                  "vc13": "bf16"}[args.config],
         "data": "synthetic (seeded)",
         "config": wl.config(),
         "hbm_gbs_step": round(per_launch_bytes * wl.units_per_step / wl.points * args.steps / sec / 1e9, 2),

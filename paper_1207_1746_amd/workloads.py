@@ -43,6 +43,14 @@ def jacobi_cube(n: int = 64, ny: int | None = None, nz: int | None = None):
     return u0, h * h
 
 
+def jacobi_rhs(n: int, ny: int | None = None, nz: int | None = None) -> np.ndarray:
+    """f ~ N(0, 1) on an (nz, ny, n) FP64 grid (right-hand side of the large
+    temporally blocked runs)."""
+    ny = ny or n
+    nz = nz or n
+    return rng(1, 1).standard_normal((nz, ny, n))
+
+
 # --------------------------------------------------------------------------- #
 # Variable-coefficient multi-grid sweep (256^3 FP32, periodic)
 # --------------------------------------------------------------------------- #
