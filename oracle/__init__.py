@@ -16,6 +16,8 @@ Bianco & Varetto):
   * ``img``             -- integer image filters (Section 1)
   * ``vc13_*``          -- fourth-order 13-point multi-field operator and its FP64
                            weighted-Jacobi solve (Section 2)
+  * ``rbgs_*``          -- red-black Gauss-Seidel / SOR passes, sweeps and solve on
+                           the Poisson problem (Section 3 stateful stencils)
   * ``sum/sumsq/maxabs``-- do_reduce with commutative operators (Section 3)
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*``
@@ -70,6 +72,8 @@ def lib():
                                       _dp, _dp, _dp]
         L.oracle_img.argtypes = [_L, _L, _L, _u8p, ctypes.c_int, _u8p, _i16p]
         L.oracle_vc13_apply.argtypes = [_L, _L, _L, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.oracle_rbgs_pass.argtypes = [_L, _L, _L, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.oracle_vc13_diag.argtypes = [_L, _L, _L, _dp, ctypes.c_double, _dp]
         for f in ("oracle_sum", "oracle_sumsq", "oracle_maxabs"):
             getattr(L, f).argtypes = [_dp, _L]
@@ -142,6 +146,48 @@ def wjacobi_sweep(u, f=None, omega=1.0, h2=1.0, bc=DIRICHLET, bcv=0.0, ndim=3):
                          float(omega), float(h2), int(bc), float(bcv), _ptr(unew), _ptr(upd),
                          _ptr(res))
     return unew, upd, res
+
+
+def rbgs_pass(u, f=None, omega=1.0, h2=1.0, colour=0, bcv=0.0):
+    """One colour pass of red-black relaxation on Lap_h u = f (Dirichlet bcv);
+    returns (u after the pass, update at the pass's points, residual before
+    the update at the pass's points)."""
+    u = _f64(u).copy()
+    nz, ny, nx = u.shape
+    fa = _f64(f) if f is not None else None
+    upd, res = np.empty_like(u), np.empty_like(u)
+    lib().oracle_rbgs_pass(nx, ny, nz, _ptr(u), _ptr(fa) if fa is not None else None, float(omega),
+                           float(h2), float(bcv), int(colour), _ptr(upd), _ptr(res))
+    return u, upd, res
+
+
+def rbgs_sweep(u, f=None, omega=1.0, h2=1.0, bcv=0.0):
+    """One red-black Gauss-Seidel (omega = 1) or SOR sweep: the red points
+    ((i+j+k) even), then the black points with the new red values."""
+    u, _, _ = rbgs_pass(u, f, omega, h2, 0, bcv)
+    u, _, _ = rbgs_pass(u, f, omega, h2, 1, bcv)
+    return u
+
+
+def rbgs_solve(f, h2: float, omega: float, rtol: float, check_every: int, max_sweeps: int):
+    """Red-black relaxation on Lap_h u = f (Dirichlet 0) from u = 0, checked
+    after every chunk of ``check_every`` sweeps: stops when the residual of
+    the current u satisfies ||f - Lap_h u||_2 <= rtol ||f||_2.
+    Returns (u, sweeps, rel_residual, converged)."""
+    f = _f64(f)
+    u = np.zeros_like(f)
+    fn = np.sqrt(sumsq(f))
+    sweeps = 0
+    rel = float("inf")
+    while sweeps < max_sweeps:
+        for _ in range(check_every):
+            u = rbgs_sweep(u, f, omega, h2)
+        sweeps += check_every
+        _, _, res = wjacobi_sweep(u, f, 1.0, h2)
+        rel = float(np.sqrt(sumsq(res)) / fn)
+        if rel <= rtol:
+            return u, sweeps, rel, True
+    return u, sweeps, rel, False
 
 
 def jacobi_run(u0, nsweeps: int, f=None, omega=1.0, h2=1.0, bc=DIRICHLET, bcv=0.0, ndim=3):

@@ -159,6 +159,49 @@ void oracle_wjacobi(int ndim, long nx, long ny, long nz, const double *u,
 }
 
 /* ------------------------------------------------------------------------ */
+/* One colour pass of red-black (over-)relaxation on the 3D Poisson problem
+ * Lap_h u = f (the stateful-stencil use of Section 3: the operator queries
+ * the index of the point it updates).  A point (i, j, k) has colour
+ * (i + j + k) mod 2; the pass updates the points of colour `colour` in place,
+ *   u(p) <- (1 - omega) u(p) + omega (S - h2 f(p)) / 6,
+ * S the sum of the 6 neighbours, reads outside the interior giving the
+ * Dirichlet value bcv.  Every new value is computed from the values at the
+ * start of the pass (the neighbours of a point all have the other colour, so
+ * the order of the updates within a colour does not matter).  Nullable
+ * outputs at the updated points (0 elsewhere):
+ *   upd = new - old,  res = f - (S - 6 u_old) / h2  (residual before the update). */
+void oracle_rbgs_pass(long nx, long ny, long nz, double *u, const double *f, double omega,
+                      double h2, double bcv, int colour, double *upd, double *res)
+{
+    long n = nx * ny * nz;
+    double *nu = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                long p = (k * ny + j) * nx + i;
+                nu[p] = u[p];
+                if (upd) upd[p] = 0.0;
+                if (res) res[p] = 0.0;
+                if ((i + j + k) % 2 != colour) continue;
+                double s = fetch3(u, nx, ny, nz, i + 1, j, k, ORC_DIRICHLET, bcv);
+                s = s + fetch3(u, nx, ny, nz, i - 1, j, k, ORC_DIRICHLET, bcv);
+                s = s + fetch3(u, nx, ny, nz, i, j + 1, k, ORC_DIRICHLET, bcv);
+                s = s + fetch3(u, nx, ny, nz, i, j - 1, k, ORC_DIRICHLET, bcv);
+                s = s + fetch3(u, nx, ny, nz, i, j, k + 1, ORC_DIRICHLET, bcv);
+                s = s + fetch3(u, nx, ny, nz, i, j, k - 1, ORC_DIRICHLET, bcv);
+                double fv = f ? f[p] : 0.0;
+                double avg = (s - h2 * fv) / 6.0;
+                double un = (1.0 - omega) * u[p] + omega * avg;
+                nu[p] = un;
+                if (upd) upd[p] = un - u[p];
+                if (res) res[p] = fv - (s - 6.0 * u[p]) / h2;
+            }
+    memcpy(u, nu, sizeof(double) * (size_t)n);
+    free(nu);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One sweep of the variable-coefficient 7-point operator over 9 input grids
  * (u, c0..c6, s) writing 3 output grids (Section 2: real codes take 5 to 15
  * grids at once).  Offsets e0 = 0, e1..e6 = +x, -x, +y, -y, +z, -z; c_k is
