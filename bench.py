@@ -39,6 +39,7 @@ KERNEL_SOURCES = {
     "image_8192_u8": [_CS + f for f in ("kcommon.h", "k_image.hip")],
     "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
     "wjacobi_tb_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "tb7.h", "k_sweep_tb.hip")],
+    "rbgs_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h", "k_sweep_wjacobi.hip")],
     "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "zq13.h", "ops.h", "sweeps_common.h",
                                   "k_sweep_vc13a.hip")],
 }
@@ -293,6 +294,83 @@ class JacobiTB:
                 "sample": f"{reps} single FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
 
 
+class RBGS:
+    """Red-black relaxation on a 512^3 FP64 cube with a right-hand side,
+    Dirichlet 0: a step is 8 sweeps (16 in-place colour passes).  Beside it,
+    one Poisson request at N = 192 is solved to 1e-8 by weighted Jacobi
+    (omega 6/7) and by optimal red-black SOR (reported as extras)."""
+    key = "rbgs_512"
+    bytes_per_point = 24  # per colour pass: u and f read, u written
+
+    def __init__(self, ctx, n=512, sweeps=8):
+        import torch
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G, self.W = G, W
+        self.n, self.sweeps = n, sweeps
+        u0, self.h2 = W.jacobi_cube(n)
+        f = W.jacobi_rhs(n)
+        self.host = (u0, f)
+        self.u = ctx.grid(u0.shape, G.F64, halo=1, data=u0)
+        self.f = ctx.grid(u0.shape, G.F64, halo=0, data=f)
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        self.points = n ** 3
+        self.units_per_step = self.points * sweeps
+        self.unit = "Gpts/s"
+        self.omega = 1.9
+        self.extra = {}
+
+    def step(self, ev=None):
+        G = self.G
+        for q in range(2 * self.sweeps):
+            last = q == 2 * self.sweeps - 1
+            if ev is not None and not last:
+                ev.begin()
+            self.ctx.do_all(G.K_RBGS, [self.u, self.f], [self.u], p=(self.omega, self.h2, q % 2),
+                            reduce=(G.R_L2, G.RV_UPDATE) if last else None,
+                            dev_result=self.res if last else None)
+            if ev is not None and not last:
+                ev.end()
+
+    def after(self):
+        G, W = self.G, self.W
+        req = W.poisson_requests(count=1, qps=float("inf"), nmin=192, nmax=192, seed_index=7)[0]
+        _, f = W.poisson_fields(req)
+        gf = self.ctx.grid(f.shape, G.F64, halo=0, data=f)
+        out = {}
+        for name, kind, omega in (("weighted_jacobi", G.K_WJACOBI, 6 / 7), ("rb_gauss_seidel", G.K_RBGS, 1.0),
+                                  ("rb_sor_optimal", G.K_RBGS, 0.0)):
+            u = self.ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+            t0 = time.perf_counter()
+            st = self.ctx.solve(kind, [u], [gf], omega=omega, h2=req.h2, rtol=1e-8, check_every=16)
+            sec = time.perf_counter() - t0
+            out[name] = {"sweeps": st["sweeps"], "seconds": round(sec, 4),
+                         "rel_residual": st["rel_residual"]}
+        self.extra = {"poisson_192_to_1e-8": out}
+
+    def config(self):
+        return {"workload": f"red-black SOR (omega {self.omega}) 7-point {self.n}^3 FP64 with right-hand side, "
+                            f"Dirichlet 0, {self.sweeps} sweeps = {2 * self.sweeps} in-place colour passes "
+                            f"+ L2 of the last update", "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        u0, f = self.host
+        t0 = time.perf_counter()
+        reps = 0
+        u = u0
+        while True:
+            u = oracle.rbgs_sweep(u, f, self.omega, self.h2)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} red-black FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
+
+
 class Image:
     key = "image_8192_u8"
     bytes_per_point = 4  # read 1 B, write 1 B box + 2 B Laplacian
@@ -521,8 +599,8 @@ class VC13:
                 "sample": f"{reps} single-field FP64 applies in {dt:.1f} s (scaled to 5 fields)"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "image": Image, "serve": Serve,
-             "reduce": Reduce,
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs": RBGS, "image": Image,
+             "serve": Serve, "reduce": Reduce,
              "vc13": VC13}
 
 
@@ -643,7 +721,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "image": "u8", "reduce": "f64",
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "rbgs": "f64", "image": "u8", "reduce": "f64",
                   "vc13": "bf16"}[args.config],
         "data": "synthetic (seeded)",
         "config": wl.config(),

@@ -142,7 +142,15 @@ typedef struct gscl_batch gscl_batch;
  *   Dirichlet or periodic rule (CLAMP: GSCL_ERR_UNSUPPORTED).  The result is
  *   bitwise the one k separate WJACOBI sweeps give; fused operands refer to
  *   the last sweep (UPDATE = u_k - u_{k-1}, RESIDUAL of u_{k-1}).  Its tile
- *   uses only cz (output planes per block).                                 */
+ *   uses only cz (output planes per block).
+ * GSCL_K_RBGS (Section 3 stateful stencils: red-black Gauss-Seidel / SOR):
+ *   one colour pass in place.  in = {u} or {u, f}; out = {u} (the same grid
+ *   as in[0]; f may not overlap it); p[0] = omega, p[1] = h^2, p[2] = colour.
+ *   Points with (i+j+k) mod 2 == colour get (1-omega) u + omega (S - h^2 f)/6
+ *   from their neighbours (all of the other colour, unchanged by the pass);
+ *   the others keep their value.  ndim 3, F64 or F32, Dirichlet rule.  Fused
+ *   operands cover the pass's points (UPDATE = u' - u, RESIDUAL before the
+ *   update), 0 elsewhere.  Tiles as GSCL_K_WJACOBI.                         */
 enum {
     GSCL_K_LINEAR = 0,
     GSCL_K_WJACOBI = 1,
@@ -152,7 +160,8 @@ enum {
     GSCL_K_VC13_JACOBI = 5,
     GSCL_K_VC13_RESID = 6,
     GSCL_K_POISSON_RESID = 7,
-    GSCL_K_WJACOBI_TB = 8
+    GSCL_K_WJACOBI_TB = 8,
+    GSCL_K_RBGS = 9
 };
 
 typedef struct {
@@ -260,15 +269,19 @@ int gscl_graph_destroy(gscl_graph *graph);
 /* ---- solver (Section 5.2: do_all + fused convergence check until done) ---- */
 enum { GSCL_PREC_F64 = 0, GSCL_PREC_F32_IR = 1, GSCL_PREC_BF16_IR = 2, GSCL_PREC_F16_IR = 3 };
 typedef struct {
-    double omega;               /* Jacobi weight */
-    double h2;                  /* WJACOBI: grid spacing squared */
+    double omega;               /* Jacobi weight; RBGS: relaxation weight in [0, 2),
+                                   0 = the optimal SOR weight of the model problem */
+    double h2;                  /* WJACOBI, RBGS: grid spacing squared */
     double kappa;               /* VC13: operator constant */
     double rtol;                /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int32_t check_every;        /* sweeps per chunk (>= 2, even); the last sweep of
                                    each chunk carries the residual check */
     int32_t precision;          /* GSCL_PREC_* */
     int32_t inner_sweeps;       /* IR: low-precision sweeps per outer step */
-    int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f) or
+    int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f),
+                                   GSCL_K_RBGS (Poisson by red-black Gauss-Seidel /
+                                   SOR, F64, in place; the check follows each chunk
+                                   as a separate residual pass), or
                                    GSCL_K_VC13_APPLY (A x = b, several fields) */
     int64_t max_sweeps;
 } gscl_solve_desc;

@@ -491,6 +491,34 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             he = gk::launch_wjacobi(a, dt, g0->d.ndim, n_in == 2, t, red, c->stream, &nblocks);
             break;
         }
+        case GSCL_K_RBGS: {
+            if (n_in < 1 || n_in > 2 || n_out != 1) return gscl_fail(GSCL_ERR_ARG, "RBGS takes {u[, f]} -> {u}");
+            if (dt != GSCL_F64 && dt != GSCL_F32) return gscl_fail(GSCL_ERR_DTYPE, "RBGS needs F64 or F32 grids");
+            if ((rc = check_dtypes(in, 0, n_in, dt, "input")) || (rc = check_dtypes(out, 0, n_out, dt, "output")))
+                return rc;
+            // in place: the output is the grid the pass reads
+            if (out[0]->ptr != in[0]->ptr) return gscl_fail(GSCL_ERR_ARG, "RBGS updates u in place: out[0] must be in[0]");
+            if (in[0]->d.halo < 1) return gscl_fail(GSCL_ERR_HALO, "RBGS reads u at offset 1 but its halo is %d", in[0]->d.halo);
+            if (in[0]->d.ndim != 3) return gscl_fail(GSCL_ERR_SHAPE, "RBGS needs ndim 3");
+            if (in[0]->d.bc != GSCL_BC_DIRICHLET) return gscl_fail(GSCL_ERR_UNSUPPORTED, "RBGS uses the Dirichlet rule");
+            if (n_in == 2 && overlaps(in[1], out[0])) return gscl_fail(GSCL_ERR_ALIAS, "RBGS right-hand side overlaps u");
+            if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "RBGS needs h^2 != 0 in p[1]");
+            if (op->p[2] != 0.0 && op->p[2] != 1.0) return gscl_fail(GSCL_ERR_ARG, "RBGS colour p[2] must be 0 or 1");
+            double p[8] = {op->p[0], op->p[1], 1.0 / op->p[1], op->p[2], 0, 0, 0, 0};
+            fill_targs(a, g0, p);
+            a.nb[0] = in[0]->ptr;
+            if (n_in == 2) a.pa[0] = in[1]->ptr;
+            a.out[0] = out[0]->ptr;
+            a.operand = red ? fused->operand : 0;
+            gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
+            if (red) {
+                t = reduce_tile(t, g0->d);
+                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra);
+            }
+            he = gk::launch_rbgs(a, dt, n_in == 2, t, red, c->stream, &nblocks);
+            break;
+        }
         case GSCL_K_WJACOBI_TB: {
             if (n_in < 1 || n_in > 2 || n_out != 1)
                 return gscl_fail(GSCL_ERR_ARG, "WJACOBI_TB takes {u[, f]} -> {u_k}");

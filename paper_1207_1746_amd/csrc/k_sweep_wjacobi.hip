@@ -30,6 +30,14 @@ hipError_t launch_wjacobi(TArgs& a, int dtype, int ndim, bool has_f, const TileC
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_rbgs(TArgs& a, int dtype, bool has_f, const TileCfg& c, bool red, hipStream_t s, int* nb) {
+    if (dtype == DT_F64)
+        return has_f ? run7<OpRBGS<double, true>>(a, c, red, s, nb) : run7<OpRBGS<double, false>>(a, c, red, s, nb);
+    if (dtype == DT_F32)
+        return has_f ? run7<OpRBGS<float, true>>(a, c, red, s, nb) : run7<OpRBGS<float, false>>(a, c, red, s, nb);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_poisson_resid(TArgs& a, const TileCfg& c, bool red, hipStream_t s, int* nb) {
     return run7<OpPoissonResid>(a, c, red, s, nb);
 }

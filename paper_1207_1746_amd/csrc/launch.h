@@ -22,6 +22,9 @@ hipError_t launch_wjacobi(TArgs& a, int dtype, int ndim, bool has_f, const TileC
                           hipStream_t s, int* nblocks);
 hipError_t launch_varcoef7(TArgs& a, int dtype, const TileCfg& c, bool red, hipStream_t s,
                            int* nblocks);
+// Red-black relaxation, one colour pass in place (a.nb[0] == a.out[0]).
+hipError_t launch_rbgs(TArgs& a, int dtype, bool has_f, const TileCfg& c, bool red, hipStream_t s,
+                       int* nblocks);
 hipError_t launch_vc13_apply(TArgs& a, int dtype, int nfields, const TileCfg& c, bool red,
                              hipStream_t s, int* nblocks);
 hipError_t launch_vc13_jacobi(TArgs& a, int dtype_nb, int dtype_g, int dtype_c, int nfields,

@@ -50,6 +50,46 @@ struct OpWJacobi {
     }
 };
 
+// Red-black relaxation, one colour pass in place (Section 3: a stateful
+// stencil queries the index of the point it updates, as red-black
+// Gauss-Seidel needs).  Points of colour p[3] ((i+j+k) mod 2) get the
+// weighted-Jacobi value of their neighbours, which all have the other colour
+// and do not change during the pass; the other points keep their value.
+// Reductions see the pass's points only (0 elsewhere).  3D, Dirichlet.
+//   p[0] = omega, p[1] = h^2, p[2] = 1/h^2, p[3] = colour.
+template <class T_, bool HAS_F>
+struct OpRBGS {
+    using T = T_; using SN = T_; using SA = T_; using SB = T_; using SO = T_;
+    static constexpr int NF = 1, NA = HAS_F ? 1 : 0, NB = 0, NO = 1, NR = 1, R = 1, NDIM = 3;
+    static constexpr bool SEPARABLE = false;
+    template <class ST, class AV, class BV>
+    __device__ __forceinline__ static void apply(const ST& st, const AV& av, const BV&,
+                                                 const double* p, T (&o)[1], double (&rv)[1],
+                                                 int operand) {
+#pragma clang fp contract(off)
+        const T u = st.c[0];
+        T s = st.xp[0][0] + st.xm[0][0];
+        s = s + st.yp[0][0];
+        s = s + st.ym[0][0];
+        s = s + st.zp[0][0];
+        s = s + st.zm[0][0];
+        const T fv = HAS_F ? av[0] : T(0);
+        const T omega = (T)p[0], h2 = (T)p[1], ih2 = (T)p[2];
+        const T avg = (s - h2 * fv) * (T(1) / T(6));
+        const T un = (T(1) - omega) * u + omega * avg;
+        const bool mine = ((st.ix + st.iy + st.iz) & 1) == (int)p[3];
+        o[0] = mine ? un : u;
+        double r;
+        if (operand == RV_RESIDUAL)
+            r = (double)(fv - (s - T(6) * u) * ih2);
+        else if (operand == RV_UPDATE)
+            r = (double)(un - u);
+        else
+            r = (double)un;
+        rv[0] = mine ? r : 0.0;
+    }
+};
+
 // Residual of the Poisson problem Lap_h x = f in FP64, stored as F32 (the
 // right-hand side of the low-precision correction sweeps of iterative
 // refinement): r = f - (S - 6 x) / h^2.  p[2] = 1/h^2.

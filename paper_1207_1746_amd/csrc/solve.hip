@@ -79,6 +79,7 @@ struct Cleanup {
 extern "C" size_t gscl_solve_workspace_bytes(const gscl_solve_desc* sd, const gscl_grid* x, int nf) {
     if (!sd || !grid_ok(x) || nf < 1) return 0;
     const gscl_grid_desc& d = x->d;
+    if (sd->kind == GSCL_K_RBGS) return bytes_like(d, GSCL_F32) + 256;  // residual grid
     if (sd->precision == GSCL_PREC_F64) return bytes_like(d, GSCL_F64) * nf + 256;
     const int s = inner_dtype(sd->precision);
     if (sd->kind == GSCL_K_WJACOBI) return bytes_like(d, GSCL_F32) * 3 + 256;
@@ -99,10 +100,13 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
     if (c->state != CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "solve outside gscl_begin/gscl_end");
     if (!sd || !x || !b || !stats) return gscl_fail(GSCL_ERR_ARG, "null argument");
     if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "solve inside graph capture");
-    const bool poisson = sd->kind == GSCL_K_WJACOBI;
+    const bool rbgs = sd->kind == GSCL_K_RBGS;
+    const bool poisson = sd->kind == GSCL_K_WJACOBI || rbgs;
     const bool vc13 = sd->kind == GSCL_K_VC13_APPLY;
-    if (!poisson && !vc13) return gscl_fail(GSCL_ERR_ARG, "solve kind must be WJACOBI or VC13_APPLY");
+    if (!poisson && !vc13) return gscl_fail(GSCL_ERR_ARG, "solve kind must be WJACOBI, RBGS or VC13_APPLY");
     if (poisson && nf != 1) return gscl_fail(GSCL_ERR_ARG, "Poisson solve takes one field");
+    if (rbgs && sd->precision != GSCL_PREC_F64) return gscl_fail(GSCL_ERR_UNSUPPORTED, "RBGS solves run in F64");
+    if (rbgs && !(sd->omega >= 0.0 && sd->omega < 2.0)) return gscl_fail(GSCL_ERR_ARG, "RBGS needs 0 <= omega < 2");
     if (vc13 && nf != 1 && nf != 5) return gscl_fail(GSCL_ERR_UNSUPPORTED, "VC13 solve takes 1 or 5 fields");
     if (vc13 && (ncoef != 10 || !coef)) return gscl_fail(GSCL_ERR_ARG, "VC13 solve needs 10 coefficient grids");
     if (sd->check_every < 2 || sd->check_every % 2) return gscl_fail(GSCL_ERR_ARG, "check_every must be even and >= 2");
@@ -173,7 +177,60 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
         return rel <= sd->rtol ? 1 : 0;
     };
 
-    if (sd->precision == GSCL_PREC_F64) {
+    if (rbgs) {
+        // Red-black relaxation in place: a chunk is S sweeps (a red and a
+        // black pass each) and then the residual of the current x, so the
+        // grid returned is the grid that was checked.  omega = 0 selects the
+        // optimal SOR weight of the model problem, 2 / (1 + sqrt(1 - rho^2)),
+        // rho = (cos(pi/(nx+1)) + cos(pi/(ny+1)) + cos(pi/(nz+1))) / 3 the
+        // Jacobi spectral radius for a uniform grid spacing.
+        double omega = sd->omega;
+        if (omega == 0.0) {
+            const double pi = 3.14159265358979323846;
+            const double rho = (cos(pi / (xd.n[0] + 1)) + cos(pi / (xd.n[1] + 1)) + cos(pi / (xd.n[2] + 1))) / 3.0;
+            omega = 2.0 / (1.0 + sqrt(1.0 - rho * rho));
+        }
+        gscl_grid* r = carve(c, xd, GSCL_F32, 0, cur, cl.grids);
+        const int S = sd->check_every;
+        if ((rc = gscl_graph_begin(c))) return rc;
+        for (int k = 0; k < 2 * S && rc == GSCL_OK; ++k) {
+            gscl_stencil_desc op;
+            memset(&op, 0, sizeof op);
+            op.kind = GSCL_K_RBGS;
+            op.p[0] = omega;
+            op.p[1] = sd->h2;
+            op.p[2] = k % 2;
+            gscl_grid* in[2] = {x[0], const_cast<gscl_grid*>(b[0])};
+            rc = gscl_do_all(c, &op, in, 2, x, 1, nullptr, nullptr);
+        }
+        if (rc == GSCL_OK) {
+            gscl_stencil_desc op;
+            memset(&op, 0, sizeof op);
+            op.kind = GSCL_K_POISSON_RESID;
+            op.p[1] = sd->h2;
+            gscl_grid* in[2] = {x[0], const_cast<gscl_grid*>(b[0])};
+            rc = gscl_do_all(c, &op, in, 2, &r, 1, &chk, nullptr);
+        }
+        gscl_graph* gr = nullptr;
+        int rc2 = gscl_graph_end(c, &gr);
+        if (rc) return rc;
+        if (rc2) return rc2;
+        cl.graph = gr;
+        rc = GSCL_ERR_NOCONV;
+        while (sweeps < sd->max_sweeps) {
+            int e = gscl_graph_launch(c, gr);
+            if (e) return e;
+            sweeps += S;
+            double res2 = 0.0;
+            if ((e = sync_read(c, &res2))) return e;
+            int d = done_check(res2);
+            if (d < 0) return d;
+            if (d == 1) {
+                rc = GSCL_OK;
+                break;
+            }
+        }
+    } else if (sd->precision == GSCL_PREC_F64) {
         std::vector<gscl_grid*> w(nf);
         for (int f = 0; f < nf; ++f) w[f] = carve(c, xd, GSCL_F64, R, cur, cl.grids);
         const int S = sd->check_every;

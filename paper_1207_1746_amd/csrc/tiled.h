@@ -43,6 +43,7 @@ template <class T, int NF, int R>
 struct Star {
     T c[NF];
     T xm[NF][R], xp[NF][R], ym[NF][R], yp[NF][R], zm[NF][R], zp[NF][R];
+    int ix, iy, iz;  // index of the point (stateful operators query it)
 };
 
 template <int N> struct AtLeast1 { static constexpr int v = N > 0 ? N : 1; };
@@ -199,6 +200,9 @@ __device__ __forceinline__ void sweep_tile(const TArgs& a, const int tile, doubl
         // gather field f's star at element v (x neighbours inside the lane's
         // vector come from registers, the rest from the staged plane)
         auto gather = [&](auto& st, int sf, int f, int v) __attribute__((always_inline)) {
+            st.ix = gx + v;
+            st.iy = gy;
+            st.iz = z;
             st.c[sf] = q[f][RZ][v];
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
