@@ -18,6 +18,9 @@ Bianco & Varetto):
                            weighted-Jacobi solve (Section 2)
   * ``rbgs_*``          -- red-black Gauss-Seidel / SOR passes, sweeps and solve on
                            the Poisson problem (Section 3 stateful stencils)
+  * ``line_recur``, ``tridiag_*`` -- ordered line iteration spaces (Section 3
+                           do_i/j/k_inc, do_i/j/k_dec): a first-order recurrence
+                           and the two passes of the Thomas algorithm
   * ``sum/sumsq/maxabs``-- do_reduce with commutative operators (Section 3)
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*``
@@ -74,6 +77,11 @@ def lib():
         L.oracle_vc13_apply.argtypes = [_L, _L, _L, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.oracle_rbgs_pass.argtypes = [_L, _L, _L, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.oracle_line_recur.argtypes = [_L, _L, _L, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                        ctypes.c_double, _dp]
+        L.oracle_tridiag_fwd.argtypes = [_L, _L, _L, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp,
+                                         _dp, _dp]
+        L.oracle_tridiag_back.argtypes = [_L, _L, _L, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.oracle_vc13_diag.argtypes = [_L, _L, _L, _dp, ctypes.c_double, _dp]
         for f in ("oracle_sum", "oracle_sumsq", "oracle_maxabs"):
             getattr(L, f).argtypes = [_dp, _L]
@@ -188,6 +196,52 @@ def rbgs_solve(f, h2: float, omega: float, rtol: float, check_every: int, max_sw
         if rel <= rtol:
             return u, sweeps, rel, True
     return u, sweeps, rel, False
+
+
+def _line_dims(a):
+    a = _f64(a)
+    if a.ndim == 2:
+        a = a[None]
+    nz, ny, nx = a.shape
+    return a, nx, ny, nz
+
+
+def line_recur(a, b, axis: int, direction: int, seed: float = 0.0):
+    """Ordered line iteration space (do_i/j/k_inc for direction +1, _dec for
+    -1 along axis 0/1/2 = i/j/k) applying out(c) = a(c) * prev + b(c)."""
+    a, nx, ny, nz = _line_dims(a)
+    b = _line_dims(b)[0]
+    out = np.empty_like(a)
+    lib().oracle_line_recur(nx, ny, nz, int(axis), int(direction), _ptr(a), _ptr(b), float(seed),
+                            _ptr(out))
+    return out
+
+
+def tridiag_fwd(lo, di, up, rhs, axis: int, direction: int):
+    """Thomas forward elimination along the lines; returns (cp, dp)."""
+    lo, nx, ny, nz = _line_dims(lo)
+    di, up, rhs = (_line_dims(x)[0] for x in (di, up, rhs))
+    cp, dp = np.empty_like(lo), np.empty_like(lo)
+    lib().oracle_tridiag_fwd(nx, ny, nz, int(axis), int(direction), _ptr(lo), _ptr(di), _ptr(up),
+                             _ptr(rhs), _ptr(cp), _ptr(dp))
+    return cp, dp
+
+
+def tridiag_back(cp, dp, axis: int, direction: int):
+    """Thomas back substitution along the lines (direction opposite to the
+    elimination); returns x."""
+    cp, nx, ny, nz = _line_dims(cp)
+    dp = _line_dims(dp)[0]
+    x = np.empty_like(cp)
+    lib().oracle_tridiag_back(nx, ny, nz, int(axis), int(direction), _ptr(cp), _ptr(dp), _ptr(x))
+    return x
+
+
+def tridiag_solve(lo, di, up, rhs, axis: int, direction: int = 1):
+    """Solve the tridiagonal system of every line: elimination along
+    `direction`, substitution back against it."""
+    cp, dp = tridiag_fwd(lo, di, up, rhs, axis, direction)
+    return tridiag_back(cp, dp, axis, -direction)
 
 
 def jacobi_run(u0, nsweeps: int, f=None, omega=1.0, h2=1.0, bc=DIRICHLET, bcv=0.0, ndim=3):

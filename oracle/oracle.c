@@ -202,6 +202,100 @@ void oracle_rbgs_pass(long nx, long ny, long nz, double *u, const double *f, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ordered line iteration spaces (Section 3: do_i_inc ... do_k_dec): along
+ * axis `axis` (0 = i, 1 = j, 2 = k) every line is processed cell by cell, in
+ * increasing index order for dir = +1 (cell c-1 before c) and decreasing for
+ * dir = -1 (cell c+1 before c); different lines are independent.  The
+ * element at position c of line (p, q) has the grid offset of (i, j, k) with
+ * the axis coordinate c.  `prev` below is the value the operator wrote at the
+ * previously processed cell of the line, or the seed before the first cell.
+ *
+ * oracle_line_recur:   out(c) = a(c) * prev + b(c),   seed = `seed`.
+ * oracle_tridiag_fwd:  forward elimination of the Thomas algorithm,
+ *   den = di(c) - lo(c) * cp_prev,  cp(c) = up(c) / den,
+ *   dp(c) = (rhs(c) - lo(c) * dp_prev) / den,   cp, dp seeded with 0.
+ * oracle_tridiag_back: back substitution, x(c) = dp(c) - cp(c) * x_prev,
+ *   x seeded with 0 (run in the opposite direction of the elimination). */
+static long line_offset(long nx, long ny, int axis, long c, long p, long q)
+{
+    /* (p, q) are the two other coordinates in (i, j, k) order */
+    long i, j, k;
+    if (axis == 0) { i = c; j = p; k = q; }
+    else if (axis == 1) { i = p; j = c; k = q; }
+    else { i = p; j = q; k = c; }
+    return (k * ny + j) * nx + i;
+}
+
+static void line_extents(long nx, long ny, long nz, int axis, long *len, long *np, long *nq)
+{
+    if (axis == 0) { *len = nx; *np = ny; *nq = nz; }
+    else if (axis == 1) { *len = ny; *np = nx; *nq = nz; }
+    else { *len = nz; *np = nx; *nq = ny; }
+}
+
+void oracle_line_recur(long nx, long ny, long nz, int axis, int dir, const double *a,
+                       const double *b, double seed, double *out)
+{
+    long len, np, nq;
+    line_extents(nx, ny, nz, axis, &len, &np, &nq);
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nq; ++q)
+        for (long p = 0; p < np; ++p) {
+            double prev = seed;
+            for (long s = 0; s < len; ++s) {
+                long c = dir > 0 ? s : len - 1 - s;
+                long o = line_offset(nx, ny, axis, c, p, q);
+                double v = a[o] * prev + b[o];
+                out[o] = v;
+                prev = v;
+            }
+        }
+}
+
+void oracle_tridiag_fwd(long nx, long ny, long nz, int axis, int dir, const double *lo,
+                        const double *di, const double *up, const double *rhs, double *cp,
+                        double *dp)
+{
+    long len, np, nq;
+    line_extents(nx, ny, nz, axis, &len, &np, &nq);
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nq; ++q)
+        for (long p = 0; p < np; ++p) {
+            double cprev = 0.0, dprev = 0.0;
+            for (long s = 0; s < len; ++s) {
+                long c = dir > 0 ? s : len - 1 - s;
+                long o = line_offset(nx, ny, axis, c, p, q);
+                double den = di[o] - lo[o] * cprev;
+                double cv = up[o] / den;
+                double dv = (rhs[o] - lo[o] * dprev) / den;
+                cp[o] = cv;
+                dp[o] = dv;
+                cprev = cv;
+                dprev = dv;
+            }
+        }
+}
+
+void oracle_tridiag_back(long nx, long ny, long nz, int axis, int dir, const double *cp,
+                         const double *dp, double *x)
+{
+    long len, np, nq;
+    line_extents(nx, ny, nz, axis, &len, &np, &nq);
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nq; ++q)
+        for (long p = 0; p < np; ++p) {
+            double prev = 0.0;
+            for (long s = 0; s < len; ++s) {
+                long c = dir > 0 ? s : len - 1 - s;
+                long o = line_offset(nx, ny, axis, c, p, q);
+                double v = dp[o] - cp[o] * prev;
+                x[o] = v;
+                prev = v;
+            }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One sweep of the variable-coefficient 7-point operator over 9 input grids
  * (u, c0..c6, s) writing 3 output grids (Section 2: real codes take 5 to 15
  * grids at once).  Offsets e0 = 0, e1..e6 = +x, -x, +y, -y, +z, -z; c_k is
