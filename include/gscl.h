@@ -150,7 +150,19 @@ typedef struct gscl_batch gscl_batch;
  *   from their neighbours (all of the other colour, unchanged by the pass);
  *   the others keep their value.  ndim 3, F64 or F32, Dirichlet rule.  Fused
  *   operands cover the pass's points (UPDATE = u' - u, RESIDUAL before the
- *   update), 0 elsewhere.  Tiles as GSCL_K_WJACOBI.                         */
+ *   update), 0 elsewhere.  Tiles as GSCL_K_WJACOBI.
+ *
+ * Operators of the ordered line iteration spaces (gscl_do_line below).  The
+ * value the operator wrote at the previously processed cell of a line is
+ * `prev` (the seed before the first cell):
+ * GSCL_K_LINE_RECUR: in = {a, b}, out = {u}: u(c) = a(c) prev + b(c);
+ *   p[0] = seed.
+ * GSCL_K_TRIDIAG_FWD (Thomas elimination): in = {lo, di, up, rhs},
+ *   out = {cp, dp}: den = di - lo cp_prev, cp = up / den,
+ *   dp = (rhs - lo dp_prev) / den, seeds 0; lo couples a cell to the
+ *   previously processed one, up to the next.
+ * GSCL_K_TRIDIAG_BACK (substitution): in = {cp, dp}, out = {x}:
+ *   x = dp - cp x_prev, seed 0; run in the opposite direction.              */
 enum {
     GSCL_K_LINEAR = 0,
     GSCL_K_WJACOBI = 1,
@@ -161,7 +173,10 @@ enum {
     GSCL_K_VC13_RESID = 6,
     GSCL_K_POISSON_RESID = 7,
     GSCL_K_WJACOBI_TB = 8,
-    GSCL_K_RBGS = 9
+    GSCL_K_RBGS = 9,
+    GSCL_K_LINE_RECUR = 10,
+    GSCL_K_TRIDIAG_FWD = 11,
+    GSCL_K_TRIDIAG_BACK = 12
 };
 
 typedef struct {
@@ -237,6 +252,19 @@ int gscl_grid_destroy(gscl_grid *grid);
 int gscl_do_all(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in, int n_in,
                 gscl_grid *const *out, int n_out, const gscl_reduce_desc *fused,
                 double *fused_result);
+/* Ordered line iteration spaces (Section 3: do_i_inc, do_j_inc, do_k_inc and
+ * do_i_dec, do_j_dec, do_k_dec): every line of the grids along `axis`
+ * (0 = i / x, 1 = j / y, 2 = k / z, which needs ndim 3) is processed cell by
+ * cell, cell c-1 before c for dir = +1 and c+1 before c for dir = -1; lines
+ * are independent and run in parallel.  Kinds GSCL_K_LINE_RECUR,
+ * GSCL_K_TRIDIAG_FWD, GSCL_K_TRIDIAG_BACK; grids F64 or F32 (one type), same
+ * extents and pitches, outputs overlapping no input and no other output.
+ * No halo is read (the seeds stand for the cell before the first).
+ * Asynchronous on the context stream; GSCL_ERR_ARG for a bad axis or
+ * direction, GSCL_ERR_DTYPE, GSCL_ERR_SHAPE, GSCL_ERR_ALIAS as for do_all. */
+int gscl_do_line(gscl_ctx *ctx, const gscl_stencil_desc *op, int axis, int dir,
+                 gscl_grid *const *in, int n_in, gscl_grid *const *out, int n_out);
+
 /* do_reduce: reduce grid a (or a - b when b is non-NULL, same extents) over
  * its interior with rd->op.  Accumulates in F64 (integers exactly). */
 int gscl_do_reduce(gscl_ctx *ctx, const gscl_reduce_desc *rd, const gscl_grid *a,

@@ -675,6 +675,55 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
     return GSCL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Ordered line iteration spaces (Section 3: do_i/j/k_inc, do_i/j/k_dec)
+// ---------------------------------------------------------------------------
+extern "C" int gscl_do_line(gscl_ctx* c, const gscl_stencil_desc* op, int axis, int dir, gscl_grid* const* in,
+                            int n_in, gscl_grid* const* out, int n_out) {
+    if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
+    if (c->state != CTX_ACTIVE)
+        return gscl_fail(GSCL_ERR_STATE, "do_line outside gscl_begin/gscl_end (context state %d)", c->state);
+    if (!op || !in || !out) return gscl_fail(GSCL_ERR_ARG, "null argument");
+    if (axis < 0 || axis > 2) return gscl_fail(GSCL_ERR_ARG, "axis must be 0, 1 or 2 (got %d)", axis);
+    if (dir != 1 && dir != -1) return gscl_fail(GSCL_ERR_ARG, "dir must be +1 or -1 (got %d)", dir);
+    int kind, nin_need, nout_need;
+    switch (op->kind) {
+        case GSCL_K_LINE_RECUR: kind = gk::LINE_RECUR; nin_need = 2; nout_need = 1; break;
+        case GSCL_K_TRIDIAG_FWD: kind = gk::LINE_TRIDIAG_FWD; nin_need = 4; nout_need = 2; break;
+        case GSCL_K_TRIDIAG_BACK: kind = gk::LINE_TRIDIAG_BACK; nin_need = 2; nout_need = 1; break;
+        default: return gscl_fail(GSCL_ERR_ARG, "kind %d is not a line operator", op->kind);
+    }
+    if (n_in != nin_need || n_out != nout_need)
+        return gscl_fail(GSCL_ERR_ARG, "line kind %d takes %d inputs and %d outputs", op->kind, nin_need, nout_need);
+    int rc = check_common(c, in, n_in, out, n_out);
+    if (rc) return rc;
+    const gscl_grid* g0 = in[0];
+    const int dt = g0->d.dtype;
+    if (dt != GSCL_F64 && dt != GSCL_F32) return gscl_fail(GSCL_ERR_DTYPE, "line operators need F64 or F32 grids");
+    if ((rc = check_dtypes(in, 0, n_in, dt, "input")) || (rc = check_dtypes(out, 0, n_out, dt, "output"))) return rc;
+    if (axis == 2 && g0->d.ndim != 3) return gscl_fail(GSCL_ERR_SHAPE, "lines along k need ndim 3");
+    for (int o = 0; o < n_out; ++o) {
+        for (int i = 0; i < n_in; ++i)
+            if (overlaps(in[i], out[o])) return gscl_fail(GSCL_ERR_ALIAS, "output %d overlaps input %d", o, i);
+        for (int o2 = 0; o2 < o; ++o2)
+            if (overlaps(out[o2], out[o])) return gscl_fail(GSCL_ERR_ALIAS, "outputs %d and %d overlap", o2, o);
+    }
+    gk::LineArgs la;
+    memset(&la, 0, sizeof la);
+    for (int i = 0; i < n_in; ++i) la.in[i] = in[i]->ptr;
+    for (int o = 0; o < n_out; ++o) la.out[o] = out[o]->ptr;
+    la.py = g0->d.pitch[0];
+    la.pz = g0->d.pitch[1];
+    la.nx = (int)g0->d.n[0];
+    la.ny = (int)g0->d.n[1];
+    la.nz = (int)g0->d.n[2];
+    la.dir = dir;
+    la.seed = op->p[0];
+    hipError_t he = gk::launch_line(la, dt == GSCL_F64 ? 0 : 1, kind, axis, c->stream);
+    if (he != hipSuccess) return gscl_hip_fail(he, "line kernel launch");
+    return GSCL_OK;
+}
+
 extern "C" int gscl_do_reduce(gscl_ctx* c, const gscl_reduce_desc* rd, const gscl_grid* a, const gscl_grid* b,
                               double* result) {
     if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");

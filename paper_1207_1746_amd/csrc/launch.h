@@ -34,6 +34,20 @@ hipError_t launch_vc13_resid(TArgs& a, int dtype_c, int nfields, const TileCfg& 
 // Blocks a tiled launch with this configuration would use.
 int tiled_blocks(const Geo& g, const TileCfg& c);
 
+// Ordered line iteration spaces: every line along `axis` (0 = x, 1 = y,
+// 2 = z) processed cell by cell in direction `dir` (+1 / -1); F64 (dtype 0)
+// or F32 (dtype 1).
+enum { LINE_RECUR = 0, LINE_TRIDIAG_FWD = 1, LINE_TRIDIAG_BACK = 2 };
+struct LineArgs {
+    const void* in[4];
+    void* out[2];
+    int64_t py, pz;   // row and plane pitch (elements)
+    int nx, ny, nz;
+    int dir;
+    double seed;      // LINE_RECUR: value before the first cell
+};
+hipError_t launch_line(LineArgs& a, int dtype, int kind, int axis, hipStream_t s);
+
 // Weighted Jacobi, k sweeps per pass (temporal blocking), 3D, F64 (dtype 0)
 // or F32 (dtype 1), Dirichlet or periodic; k in 1..TB_KMAX.
 struct TBArgs;
