@@ -40,6 +40,7 @@ KERNEL_SOURCES = {
     "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
     "wjacobi_tb_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "tb7.h", "k_sweep_tb.hip")],
     "rbgs_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h", "k_sweep_wjacobi.hip")],
+    "tridiag_512": [_CS + f for f in ("kcommon.h", "launch.h", "k_line.hip")],
     "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "zq13.h", "ops.h", "sweeps_common.h",
                                   "k_sweep_vc13a.hip")],
 }
@@ -371,6 +372,61 @@ class RBGS:
                 "sample": f"{reps} red-black FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
 
 
+class Tridiag:
+    """Ordered line iteration spaces: tridiagonal solves along k (do_k_inc
+    elimination, do_k_dec substitution) for every column of a 512^3 FP64
+    grid (diagonally dominant systems)."""
+    key = "tridiag_512"
+    bytes_per_point = 48  # elimination: lo, di, up, rhs read; cp, dp written
+
+    def __init__(self, ctx, n=512):
+        import torch
+        import paper_1207_1746_amd as G
+        self.G = G
+        shape = (n, n, n)
+        gen = torch.Generator(device="cuda").manual_seed(12071746)
+        self.grids = []
+        for lo, hi in ((-1.0, 1.0), (2.5, 3.5), (-1.0, 1.0), (-1.0, 1.0)):
+            g = ctx.grid(shape, G.F64, halo=0)
+            g.view.copy_(torch.rand(shape, dtype=torch.float64, device="cuda", generator=gen) * (hi - lo) + lo)
+            self.grids.append(g)
+        self.cp, self.dp, self.x = (ctx.grid(shape, G.F64, halo=0) for _ in range(3))
+        self.ctx, self.n = ctx, n
+        self.points = n ** 3
+        self.units_per_step = self.points
+        self.unit = "Gpts/s"
+
+    def step(self, ev=None):
+        G = self.G
+        if ev is not None:
+            ev.begin()
+        self.ctx.do_line(G.K_TRIDIAG_FWD, 2, 1, self.grids, [self.cp, self.dp])
+        if ev is not None:
+            ev.end()
+        self.ctx.do_line(G.K_TRIDIAG_BACK, 2, -1, [self.cp, self.dp], [self.x])
+
+    def config(self):
+        return {"workload": f"tridiagonal solves along k for {self.n}^2 columns of {self.n} levels, FP64 "
+                            f"(do_k_inc elimination + do_k_dec substitution)", "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import numpy as np
+        import oracle
+        m = 64  # a bounded sample: 64 x 64 columns of the full depth
+        arrs = [g.view[:, :m, :m].cpu().numpy() for g in self.grids]
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.tridiag_solve(*arrs, 2, 1)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.n * m * m * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} solves of 64 x 64 columns x {self.n} levels in {dt:.1f} s"}
+
+
 class Image:
     key = "image_8192_u8"
     bytes_per_point = 4  # read 1 B, write 1 B box + 2 B Laplacian
@@ -599,7 +655,8 @@ class VC13:
                 "sample": f"{reps} single-field FP64 applies in {dt:.1f} s (scaled to 5 fields)"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs": RBGS, "image": Image,
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs": RBGS, "tridiag": Tridiag,
+             "image": Image,
              "serve": Serve, "reduce": Reduce,
              "vc13": VC13}
 
@@ -721,7 +778,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "rbgs": "f64", "image": "u8", "reduce": "f64",
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "rbgs": "f64", "tridiag": "f64",
+                  "image": "u8", "reduce": "f64",
                   "vc13": "bf16"}[args.config],
         "data": "synthetic (seeded)",
         "config": wl.config(),
