@@ -21,6 +21,9 @@ Bianco & Varetto):
   * ``line_recur``, ``tridiag_*`` -- ordered line iteration spaces (Section 3
                            do_i/j/k_inc, do_i/j/k_dec): a first-order recurrence
                            and the two passes of the Thomas algorithm
+  * ``diamond_recur``, ``gs2d_sweep`` -- the diamond iteration space (Section 3
+                           do_diamond, 2D): a two-predecessor recurrence and a
+                           lexicographic Gauss-Seidel / SOR sweep
   * ``sum/sumsq/maxabs``-- do_reduce with commutative operators (Section 3)
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*``
@@ -82,6 +85,8 @@ def lib():
         L.oracle_tridiag_fwd.argtypes = [_L, _L, _L, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp,
                                          _dp, _dp]
         L.oracle_tridiag_back.argtypes = [_L, _L, _L, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_diamond_recur.argtypes = [_L, _L, _L, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.oracle_gs2d.argtypes = [_L, _L, _L, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.oracle_vc13_diag.argtypes = [_L, _L, _L, _dp, ctypes.c_double, _dp]
         for f in ("oracle_sum", "oracle_sumsq", "oracle_maxabs"):
             getattr(L, f).argtypes = [_dp, _L]
@@ -242,6 +247,27 @@ def tridiag_solve(lo, di, up, rhs, axis: int, direction: int = 1):
     `direction`, substitution back against it."""
     cp, dp = tridiag_fwd(lo, di, up, rhs, axis, direction)
     return tridiag_back(cp, dp, axis, -direction)
+
+
+def diamond_recur(a, b, c, seed: float = 0.0):
+    """Diamond iteration space (cells (i-1, j), (i, j-1) before (i, j); 2D
+    layers) applying out = a * out(i-1, j) + b * out(i, j-1) + c."""
+    a, nx, ny, nl = _line_dims(a)
+    b, c = _line_dims(b)[0], _line_dims(c)[0]
+    out = np.empty_like(a)
+    lib().oracle_diamond_recur(nx, ny, nl, _ptr(a), _ptr(b), _ptr(c), float(seed), _ptr(out))
+    return out
+
+
+def gs2d_sweep(u, f=None, omega=1.0, h2=1.0, bcv=0.0):
+    """One lexicographic Gauss-Seidel / SOR sweep on the 2D 5-point Poisson
+    problem (a diamond-ordered operator); returns the new grid."""
+    u, nx, ny, nl = _line_dims(u)
+    u = u.copy()
+    fa = _line_dims(f)[0] if f is not None else None
+    lib().oracle_gs2d(nx, ny, nl, _ptr(u), _ptr(fa) if fa is not None else None, float(omega), float(h2),
+                      float(bcv))
+    return u
 
 
 def jacobi_run(u0, nsweeps: int, f=None, omega=1.0, h2=1.0, bc=DIRICHLET, bcv=0.0, ndim=3):

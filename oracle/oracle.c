@@ -296,6 +296,54 @@ void oracle_tridiag_back(long nx, long ny, long nz, int axis, int dir, const dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* The diamond iteration space (Section 3: cells (i-1, j) and (i, j-1) are
+ * processed before cell (i, j); 2D, every layer independent).  Row-major
+ * order (j outer, i inner) is one order that respects it, and the operators
+ * below read only those two predecessors' new values, so every order that
+ * respects it gives these results.
+ *
+ * oracle_diamond_recur: out(i,j) = a(i,j) out(i-1,j) + b(i,j) out(i,j-1)
+ *   + c(i,j), reads before the first row or column giving `seed`.
+ * oracle_gs2d: one lexicographic Gauss-Seidel / SOR sweep in place on the 2D
+ *   5-point Poisson problem Lap_h u = f with Dirichlet value bcv:
+ *   u(i,j) <- (1 - omega) u(i,j) + omega (W + S + E + N - h2 f) / 4, where
+ *   W = u(i-1,j) and S = u(i,j-1) are already updated and E = u(i+1,j),
+ *   N = u(i,j+1) are not. */
+void oracle_diamond_recur(long nx, long ny, long nl, const double *a, const double *b,
+                          const double *c, double seed, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < nl; ++l)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                long p = (l * ny + j) * nx + i;
+                double w = i > 0 ? out[p - 1] : seed;
+                double s = j > 0 ? out[p - nx] : seed;
+                out[p] = a[p] * w + b[p] * s + c[p];
+            }
+}
+
+void oracle_gs2d(long nx, long ny, long nl, double *u, const double *f, double omega, double h2,
+                 double bcv)
+{
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < nl; ++l)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                long p = (l * ny + j) * nx + i;
+                double w = i > 0 ? u[p - 1] : bcv;
+                double s = j > 0 ? u[p - nx] : bcv;
+                double e = i + 1 < nx ? u[p + 1] : bcv;
+                double n = j + 1 < ny ? u[p + nx] : bcv;
+                double sum = w + s;
+                sum = sum + e;
+                sum = sum + n;
+                double fv = f ? f[p] : 0.0;
+                u[p] = (1.0 - omega) * u[p] + omega * ((sum - h2 * fv) / 4.0);
+            }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One sweep of the variable-coefficient 7-point operator over 9 input grids
  * (u, c0..c6, s) writing 3 output grids (Section 2: real codes take 5 to 15
  * grids at once).  Offsets e0 = 0, e1..e6 = +x, -x, +y, -y, +z, -z; c_k is
