@@ -162,7 +162,17 @@ typedef struct gscl_batch gscl_batch;
  *   dp = (rhs - lo dp_prev) / den, seeds 0; lo couples a cell to the
  *   previously processed one, up to the next.
  * GSCL_K_TRIDIAG_BACK (substitution): in = {cp, dp}, out = {x}:
- *   x = dp - cp x_prev, seed 0; run in the opposite direction.              */
+ *   x = dp - cp x_prev, seed 0; run in the opposite direction.
+ *
+ * Operators of the diamond iteration space (gscl_do_diamond below):
+ * GSCL_K_DIAMOND_RECUR: in = {a, b, c}, out = {u}:
+ *   u(i,j) = a u(i-1,j) + b u(i,j-1) + c, reads before the first row or
+ *   column giving p[0] (seed).
+ * GSCL_K_GS2D: lexicographic Gauss-Seidel / SOR sweep in place on the 2D
+ *   5-point Poisson problem: in = {u} or {u, f}, out = {u} (the same grid);
+ *   u <- (1 - omega) u + omega (W + S + E + N - h^2 f) / 4 with W = u(i-1,j),
+ *   S = u(i,j-1) already updated and E, N not; reads outside the grid give
+ *   u's Dirichlet value.  p[0] = omega, p[1] = h^2.                          */
 enum {
     GSCL_K_LINEAR = 0,
     GSCL_K_WJACOBI = 1,
@@ -176,7 +186,9 @@ enum {
     GSCL_K_RBGS = 9,
     GSCL_K_LINE_RECUR = 10,
     GSCL_K_TRIDIAG_FWD = 11,
-    GSCL_K_TRIDIAG_BACK = 12
+    GSCL_K_TRIDIAG_BACK = 12,
+    GSCL_K_DIAMOND_RECUR = 13,
+    GSCL_K_GS2D = 14
 };
 
 typedef struct {
@@ -264,6 +276,17 @@ int gscl_do_all(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in
  * direction, GSCL_ERR_DTYPE, GSCL_ERR_SHAPE, GSCL_ERR_ALIAS as for do_all. */
 int gscl_do_line(gscl_ctx *ctx, const gscl_stencil_desc *op, int axis, int dir,
                  gscl_grid *const *in, int n_in, gscl_grid *const *out, int n_out);
+
+/* The diamond iteration space (Section 3: do_diamond, 2D): cells (i-1, j) and
+ * (i, j-1) are processed before (i, j); the layers of a 2D layered grid are
+ * independent.  Kinds GSCL_K_DIAMOND_RECUR and GSCL_K_GS2D; grids ndim 2, F64
+ * or F32 (one type), same extents and pitches.  Outputs may not overlap
+ * inputs, except that GS2D updates in[0] in place (out[0] must be in[0]).
+ * One block walks the anti-diagonals of one layer, so a single large layer
+ * runs on one CU; many layers run in parallel.  Asynchronous on the context
+ * stream; errors as for gscl_do_line. */
+int gscl_do_diamond(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in, int n_in,
+                    gscl_grid *const *out, int n_out);
 
 /* do_reduce: reduce grid a (or a - b when b is non-NULL, same extents) over
  * its interior with rd->op.  Accumulates in F64 (integers exactly). */

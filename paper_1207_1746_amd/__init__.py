@@ -26,7 +26,8 @@ OK, ERR_ARG, ERR_STATE, ERR_SHAPE, ERR_HALO, ERR_ALIAS, ERR_DTYPE, ERR_NOMEM, ER
 F64, F32, F16, BF16, U8, I16, U32 = range(7)
 DIRICHLET, PERIODIC, CLAMP = 0, 1, 2
 K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_VC13_RESID, \
-    K_POISSON_RESID, K_WJACOBI_TB, K_RBGS, K_LINE_RECUR, K_TRIDIAG_FWD, K_TRIDIAG_BACK = range(13)
+    K_POISSON_RESID, K_WJACOBI_TB, K_RBGS, K_LINE_RECUR, K_TRIDIAG_FWD, K_TRIDIAG_BACK, \
+    K_DIAMOND_RECUR, K_GS2D = range(15)
 R_SUM, R_SUMSQ, R_L2, R_MAXABS, R_ALL_LE = range(5)
 RV_OUT0, RV_UPDATE, RV_RESIDUAL = range(3)
 PREC_F64, PREC_F32_IR, PREC_BF16_IR, PREC_F16_IR = range(4)
@@ -92,6 +93,7 @@ _SIGS = {
                                    _P(ReduceDesc), _P(_f64)]),
     "gscl_do_line": (ctypes.c_int, [_vp, _P(StencilDesc), ctypes.c_int, ctypes.c_int, _P(_vp), ctypes.c_int,
                                     _P(_vp), ctypes.c_int]),
+    "gscl_do_diamond": (ctypes.c_int, [_vp, _P(StencilDesc), _P(_vp), ctypes.c_int, _P(_vp), ctypes.c_int]),
     "gscl_do_reduce": (ctypes.c_int, [_vp, _P(ReduceDesc), _vp, _vp, _P(_f64)]),
     "gscl_tile_get": (ctypes.c_int, [_vp, ctypes.c_int, _P(GridDesc), _P(Tile)]),
     "gscl_tile_set": (ctypes.c_int, [_vp, ctypes.c_int, _P(GridDesc), _P(Tile)]),
@@ -346,6 +348,16 @@ class Context:
         ho, no = _handles(outs)
         check(lib().gscl_do_line(self.handle, ctypes.byref(sd), int(axis), int(direction), hi, ni, ho, no),
               "gscl_do_line")
+
+    def do_diamond(self, kind: int, ins: Sequence[Grid], outs: Sequence[Grid], p: Sequence[float] = ()):
+        """The diamond iteration space (2D): (i-1, j) and (i, j-1) before (i, j)."""
+        sd = StencilDesc()
+        sd.kind = kind
+        for i, v in enumerate(p):
+            sd.p[i] = float(v)
+        hi, ni = _handles(ins)
+        ho, no = _handles(outs)
+        check(lib().gscl_do_diamond(self.handle, ctypes.byref(sd), hi, ni, ho, no), "gscl_do_diamond")
 
     def do_reduce(self, op: int, a: Grid, b: Grid | None = None, eps: float = 0.0,
                   dev_result=None) -> float | None:

@@ -724,6 +724,63 @@ extern "C" int gscl_do_line(gscl_ctx* c, const gscl_stencil_desc* op, int axis, 
     return GSCL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The diamond iteration space (Section 3: do_diamond, 2D)
+// ---------------------------------------------------------------------------
+extern "C" int gscl_do_diamond(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* const* in, int n_in,
+                               gscl_grid* const* out, int n_out) {
+    if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
+    if (c->state != CTX_ACTIVE)
+        return gscl_fail(GSCL_ERR_STATE, "do_diamond outside gscl_begin/gscl_end (context state %d)", c->state);
+    if (!op || !in || !out) return gscl_fail(GSCL_ERR_ARG, "null argument");
+    int kind;
+    if (op->kind == GSCL_K_DIAMOND_RECUR) {
+        kind = gk::DIAMOND_RECUR;
+        if (n_in != 3 || n_out != 1) return gscl_fail(GSCL_ERR_ARG, "DIAMOND_RECUR takes {a, b, c} -> {u}");
+    } else if (op->kind == GSCL_K_GS2D) {
+        kind = gk::DIAMOND_GS2D;
+        if (n_in < 1 || n_in > 2 || n_out != 1) return gscl_fail(GSCL_ERR_ARG, "GS2D takes {u[, f]} -> {u}");
+    } else {
+        return gscl_fail(GSCL_ERR_ARG, "kind %d is not a diamond operator", op->kind);
+    }
+    int rc = check_common(c, in, n_in, out, n_out);
+    if (rc) return rc;
+    const gscl_grid* g0 = in[0];
+    const int dt = g0->d.dtype;
+    if (dt != GSCL_F64 && dt != GSCL_F32) return gscl_fail(GSCL_ERR_DTYPE, "diamond operators need F64 or F32 grids");
+    if ((rc = check_dtypes(in, 0, n_in, dt, "input")) || (rc = check_dtypes(out, 0, n_out, dt, "output"))) return rc;
+    if (g0->d.ndim != 2) return gscl_fail(GSCL_ERR_SHAPE, "the diamond iteration space is 2D (layers allowed)");
+    if (kind == gk::DIAMOND_GS2D) {
+        if (out[0]->ptr != in[0]->ptr) return gscl_fail(GSCL_ERR_ARG, "GS2D updates u in place: out[0] must be in[0]");
+        if (n_in == 2 && overlaps(in[1], out[0])) return gscl_fail(GSCL_ERR_ALIAS, "GS2D right-hand side overlaps u");
+        if (in[0]->d.bc != GSCL_BC_DIRICHLET) return gscl_fail(GSCL_ERR_UNSUPPORTED, "GS2D uses the Dirichlet rule");
+    } else {
+        for (int i = 0; i < n_in; ++i)
+            if (overlaps(in[i], out[0])) return gscl_fail(GSCL_ERR_ALIAS, "output overlaps input %d", i);
+    }
+    gk::DiamondArgs da;
+    memset(&da, 0, sizeof da);
+    for (int i = 0; i < n_in; ++i) da.in[i] = in[i]->ptr;
+    if (kind == gk::DIAMOND_GS2D) {
+        da.in[0] = nullptr;
+        da.in[1] = n_in == 2 ? in[1]->ptr : nullptr;
+        da.p[0] = op->p[0];
+        da.p[1] = op->p[1];
+        da.p[2] = in[0]->d.bc_value;
+    } else {
+        da.p[0] = op->p[0];
+    }
+    da.out = out[0]->ptr;
+    da.py = g0->d.pitch[0];
+    da.pz = g0->d.pitch[1];
+    da.nx = (int)g0->d.n[0];
+    da.ny = (int)g0->d.n[1];
+    da.nl = (int)g0->d.n[2];
+    hipError_t he = gk::launch_diamond(da, dt == GSCL_F64 ? 0 : 1, kind, c->stream);
+    if (he != hipSuccess) return gscl_hip_fail(he, "diamond kernel launch");
+    return GSCL_OK;
+}
+
 extern "C" int gscl_do_reduce(gscl_ctx* c, const gscl_reduce_desc* rd, const gscl_grid* a, const gscl_grid* b,
                               double* result) {
     if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");

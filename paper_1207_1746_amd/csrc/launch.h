@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kcommon.h"
 #include "tiled.h"
 
@@ -47,6 +49,20 @@ struct LineArgs {
     double seed;      // LINE_RECUR: value before the first cell
 };
 hipError_t launch_line(LineArgs& a, int dtype, int kind, int axis, hipStream_t s);
+
+// The diamond iteration space on 2D layers (one block per layer walking its
+// anti-diagonals); F64 (dtype 0) or F32 (dtype 1).  RECUR: in = {a, b, c},
+// p[0] = seed.  GS2D: out = u in place, in[1] = f or null, p = {omega, h^2,
+// Dirichlet value}.
+enum { DIAMOND_RECUR = 0, DIAMOND_GS2D = 1 };
+struct DiamondArgs {
+    const void* in[3];
+    void* out;
+    int64_t py, pz;   // row pitch and layer pitch (elements)
+    int nx, ny, nl;
+    double p[4];
+};
+hipError_t launch_diamond(DiamondArgs& a, int dtype, int kind, hipStream_t s);
 
 // Weighted Jacobi, k sweeps per pass (temporal blocking), 3D, F64 (dtype 0)
 // or F32 (dtype 1), Dirichlet or periodic; k in 1..TB_KMAX.
