@@ -719,6 +719,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile", default=None, help="V,NW,cz override for the dominant kernel")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the workload's extra measurements after the timed steps (for profiling runs)")
     ap.add_argument("--print-kernel-hash", action="store_true",
                     help="print the source hash of the selected workload's dominant kernel")
     args = ap.parse_args()
@@ -797,7 +799,7 @@ def main():
         },
         "cpu_baseline": None,
     }
-    if hasattr(wl, "after"):
+    if hasattr(wl, "after") and not args.no_extras:
         wl.after()
         out["extra"] = wl.extra
     if not args.no_cpu_baseline:
