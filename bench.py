@@ -526,6 +526,18 @@ class Serve:
                                        realtime=False)
         return rep.summary()
 
+    def sor(self):
+        """The same requests solved by optimal red-black SOR in F64 (O(N)
+        sweeps instead of O(N^2)): batched (continuous batching, a residual
+        check every 8 sweeps) and one solve at a time, both closed-loop."""
+        srv = self.SV.SolveServer(self.ctx, precision=self.G.PREC_F64, sweeps_per_step=8, rtol=self.rtol,
+                                  omega=0.0, max_slots=64, method=self.G.BATCH_RBGS)
+        bat = srv.run(self._jobs(), realtime=False).summary()
+        srv.close()
+        seq = self.SV.serve_sequential(self.ctx, self._jobs(), rtol=self.rtol, omega=0.0, check_every=8,
+                                       realtime=False, kind=self.G.K_RBGS).summary()
+        return bat, seq
+
     def config(self):
         return {"workload": f"{self.count} Poisson solve requests (one seeded sample), cube sides log-uniform "
                             f"in [{self.nmin},{self.nmax}], 3 sine modes, weighted Jacobi omega=6/7 to "
@@ -695,6 +707,7 @@ def serve_main(args, ctx, wl):
     bat = wl.last["batched"]
     loaded = wl.loaded()
     seq = wl.sequential()
+    sor_bat, sor_seq = wl.sor()
     out = {"metric": METRIC, "value": round(bat["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
            "steps": 1, "warmup": 1, "ms_per_step": round(sec * 1e3, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (seeded)",
@@ -703,6 +716,7 @@ def serve_main(args, ctx, wl):
            "latency_p50_s": round(loaded["p50_s"], 4), "latency_p99_s": round(loaded["p99_s"], 4),
            "batched_closed_loop": bat, "batched_at_offered_qps": loaded, "sequential_f64_closed_loop": seq,
            "speedup_vs_sequential_f64": round(bat["solves_per_s"] / seq["solves_per_s"], 3),
+           "batched_rbsor_f64_closed_loop": sor_bat, "sequential_rbsor_f64_closed_loop": sor_seq,
            "roofline": None, "cpu_baseline": None}
     ctx.end()
     ctx.finalize()

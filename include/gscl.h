@@ -353,15 +353,21 @@ int gscl_solve(gscl_ctx *ctx, const gscl_solve_desc *sd, gscl_grid *const *x,
                void *workspace, size_t workspace_bytes, gscl_solve_stats *stats);
 
 /* ---- batched multi-grid executor (many Poisson solves in one launch) ----- */
-/* A batch holds up to max_slots independent Poisson problems (WJACOBI, F64
- * u/f, Dirichlet 0, any cube or box sizes) and sweeps all active ones with one
- * persistent kernel per sweep.  Slot state lives in device memory, so a
+/* A batch holds up to max_slots independent Poisson problems (weighted Jacobi
+ * or red-black SOR, F64 u/f, Dirichlet 0, any cube or box sizes) and sweeps
+ * all active ones with one persistent kernel per sweep (Section 3: stencils
+ * over many grids; Section 5.2: a sweep fused with its convergence check).  Slot state lives in device memory, so a
  * captured step graph stays valid while slots come and go.
  *   precision GSCL_PREC_F64: ping-pong F64 sweeps, residual fused into the
  *     last sweep of each step.
  *   precision GSCL_PREC_F32_IR: F32 correction sweeps with an F64 residual /
  *     update pass per step (iterative refinement).
+ *   method GSCL_BATCH_RBGS (precision F64): red-black SOR sweeps in place
+ *     (a red and a black colour pass each), then an F64 residual pass whose
+ *     norm applies the stopping rule to the current u; omega = 0 gives each
+ *     slot the optimal model-problem weight of its extents.
  * hbm_budget bounds the sum of admitted slot footprints (bytes). */
+enum { GSCL_BATCH_JACOBI = 0, GSCL_BATCH_RBGS = 1 };
 typedef struct {
     int32_t max_slots;
     int32_t precision;
@@ -371,6 +377,8 @@ typedef struct {
     double rtol;
     size_t hbm_budget;
     int64_t max_sweeps;         /* per request; reaching it retires as not converged */
+    int32_t method;             /* GSCL_BATCH_JACOBI (weighted Jacobi) or GSCL_BATCH_RBGS */
+    int32_t reserved;
 } gscl_batch_desc;
 typedef struct {
     int32_t state;              /* 0 free, 1 running, 2 converged, 3 failed */

@@ -31,6 +31,7 @@ K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_
 R_SUM, R_SUMSQ, R_L2, R_MAXABS, R_ALL_LE = range(5)
 RV_OUT0, RV_UPDATE, RV_RESIDUAL = range(3)
 PREC_F64, PREC_F32_IR, PREC_BF16_IR, PREC_F16_IR = range(4)
+BATCH_JACOBI, BATCH_RBGS = range(2)
 MAX_TERMS = 64
 
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -71,7 +72,7 @@ class SolveStats(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("max_slots", _i32), ("precision", _i32), ("sweeps_per_step", _i32),
                 ("use_graph", _i32), ("omega", _f64), ("rtol", _f64), ("hbm_budget", ctypes.c_size_t),
-                ("max_sweeps", _i64)]
+                ("max_sweeps", _i64), ("method", _i32), ("reserved", _i32)]
 
 
 class SlotStats(ctypes.Structure):
@@ -435,14 +436,17 @@ class Graph:
 
 
 class Batch:
-    """Batched multi-grid Poisson executor (gscl_batch_*)."""
+    """Batched multi-grid Poisson executor (gscl_batch_*).  method BATCH_JACOBI
+    sweeps weighted Jacobi (F64 or F32 refinement); BATCH_RBGS sweeps red-black
+    SOR in F64 (omega = 0: each slot's optimal model-problem weight)."""
 
     def __init__(self, ctx: Context, max_slots: int = 64, precision: int = PREC_F64,
                  sweeps_per_step: int = 32, use_graph: bool = True, omega: float = 6 / 7,
-                 rtol: float = 1e-8, hbm_budget: int = 8 << 30, max_sweeps: int = 10 ** 7):
+                 rtol: float = 1e-8, hbm_budget: int = 8 << 30, max_sweeps: int = 10 ** 7,
+                 method: int = BATCH_JACOBI):
         self.ctx = ctx
         bd = BatchDesc(max_slots, precision, sweeps_per_step, int(use_graph), omega, rtol, hbm_budget,
-                       max_sweeps)
+                       max_sweeps, method, 0)
         h = _vp()
         check(lib().gscl_batch_create(ctx.handle, ctypes.byref(bd), ctypes.byref(h)), "gscl_batch_create")
         self.handle = h

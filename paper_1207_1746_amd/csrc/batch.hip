@@ -20,6 +20,11 @@
 // * F32 refinement mode: per step an F64 residual pass (stored F32) with its
 //   norm and the stopping rule, sweeps_per_step F32 correction sweeps from
 //   d = 0, then u += d (and d reset to 0) in F64.
+// * Red-black SOR mode (F64): per step sweeps_per_step sweeps of in-place
+//   colour passes (the red points, then the black ones, each reading only
+//   the other colour), then an F64 residual pass of the current u with its
+//   norm and the stopping rule.
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -38,6 +43,7 @@ struct BSlot {
     int nx, ny, nz;
     int64_t py, pz;
     double h2, ih2;
+    double omega;            // red-black SOR weight of this slot
     double* u;
     double* u2;
     const double* f;
@@ -61,7 +67,7 @@ struct BHeader {
     int total_tiles;
 };
 
-enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2 };
+enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2, MODE_RBGS = 3 };
 
 __device__ __forceinline__ int find_slot(const BSlot* __restrict__ s, int n, int t) {
     int lo = 0, hi = n - 1;
@@ -79,6 +85,7 @@ __global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict_
                                                         double omega) {
     using OpF64 = gk::OpWJacobi<double, double, 3, true>;
     using OpF32 = gk::OpWJacobi<float, float, 3, true>;
+    using OpRB = gk::OpRBGS<double, true>;
     const int n = hdr->nslots, total = hdr->total_tiles;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int si = find_slot(slots, n, t);
@@ -111,6 +118,14 @@ __global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict_
             a.out[0] = parity ? s.u : s.u2;
             a.pa[0] = s.f;
             gk::sweep_tile<OpF64, BV, BNW, RED>(a, local, acc);
+        } else if (MODE == MODE_RBGS) {
+            // one colour pass in place; parity = colour
+            a.nb[0] = s.u;
+            a.out[0] = s.u;
+            a.pa[0] = s.f;
+            a.p[0] = s.omega;
+            a.p[3] = (double)parity;
+            gk::sweep_tile<OpRB, BV, BNW, false>(a, local, acc);
         } else if (MODE == MODE_RESID) {
             a.nb[0] = s.u;
             a.pa[0] = s.f;
@@ -266,11 +281,12 @@ struct gscl_batch {
     int persist_blocks;
 };
 
-static size_t slot_work_bytes(int precision, const gscl_grid_desc& d) {
+static size_t slot_work_bytes(const gscl_batch_desc& bd, const gscl_grid_desc& d) {
     const size_t pts = (size_t)d.pitch[1] * (size_t)d.n[2];
     const size_t r = [](size_t v) { return (v + 255) / 256 * 256; }(pts * 8);
     const size_t r4 = (pts * 4 + 255) / 256 * 256;
-    return precision == GSCL_PREC_F64 ? r : 3 * r4;
+    if (bd.method == GSCL_BATCH_RBGS) return r4;  // the residual grid only (in-place sweeps)
+    return bd.precision == GSCL_PREC_F64 ? r : 3 * r4;
 }
 
 extern "C" size_t gscl_batch_footprint(const gscl_batch* b, const int64_t n[3]) {
@@ -282,7 +298,7 @@ extern "C" size_t gscl_batch_footprint(const gscl_batch* b, const int64_t n[3]) 
     d.n[2] = n[2];
     d.dtype = GSCL_F64;
     if (gscl_grid_layout(&d)) return 0;
-    return 2 * gscl_grid_bytes(&d) + slot_work_bytes(b->desc.precision, d);
+    return 2 * gscl_grid_bytes(&d) + slot_work_bytes(b->desc, d);
 }
 
 extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_batch** out) {
@@ -292,6 +308,12 @@ extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_ba
     if (bd->max_slots < 1 || bd->max_slots > 4096) return gscl_fail(GSCL_ERR_ARG, "max_slots must be 1..4096");
     if (bd->precision != GSCL_PREC_F64 && bd->precision != GSCL_PREC_F32_IR)
         return gscl_fail(GSCL_ERR_UNSUPPORTED, "batch precision must be F64 or F32_IR");
+    if (bd->method != GSCL_BATCH_JACOBI && bd->method != GSCL_BATCH_RBGS)
+        return gscl_fail(GSCL_ERR_ARG, "unknown batch method %d", bd->method);
+    if (bd->method == GSCL_BATCH_RBGS && bd->precision != GSCL_PREC_F64)
+        return gscl_fail(GSCL_ERR_UNSUPPORTED, "red-black batches run in F64");
+    if (bd->method == GSCL_BATCH_RBGS && !(bd->omega >= 0.0 && bd->omega < 2.0))
+        return gscl_fail(GSCL_ERR_ARG, "red-black batches need 0 <= omega < 2");
     if (bd->sweeps_per_step < 2 || bd->sweeps_per_step % 2)
         return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be even and >= 2");
     if (!(bd->rtol > 0) || bd->max_sweeps < 1 || bd->hbm_budget < 4096)
@@ -413,7 +435,7 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
             break;
         }
     if (id < 0) return gscl_fail(GSCL_ERR_NOMEM, "no free slot");
-    const size_t wb = slot_work_bytes(b->desc.precision, u->d);
+    const size_t wb = slot_work_bytes(b->desc, u->d);
     const size_t fp = wb + u->bytes + f->bytes;
     if (b->footprint_used + fp > b->desc.hbm_budget)
         return gscl_fail(GSCL_ERR_NOMEM, "HBM budget exhausted (%zu + %zu > %zu bytes)", b->footprint_used, fp,
@@ -433,7 +455,16 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     s.u = (double*)u->ptr;
     s.f = (const double*)f->ptr;
     const size_t pts = (size_t)s.pz * (size_t)s.nz;
-    if (b->desc.precision == GSCL_PREC_F64) {
+    s.omega = b->desc.omega;
+    if (b->desc.method == GSCL_BATCH_RBGS) {
+        s.rh = (float*)mem;
+        if (s.omega == 0.0) {
+            // optimal SOR weight of the model problem on this slot's box
+            const double pi = 3.14159265358979323846;
+            const double rho = (cos(pi / (s.nx + 1)) + cos(pi / (s.ny + 1)) + cos(pi / (s.nz + 1))) / 3.0;
+            s.omega = 2.0 / (1.0 + sqrt(1.0 - rho * rho));
+        }
+    } else if (b->desc.precision == GSCL_PREC_F64) {
         s.u2 = (double*)mem;
     } else {
         const size_t r4 = (pts * 4 + 255) / 256 * 256;
@@ -460,7 +491,7 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     gscl_reduce_desc rd{GSCL_R_SUMSQ, 0, 0.0, &b->d_state[id].fnorm2};
     int rc = gscl_do_reduce(c, &rd, f, nullptr, nullptr);
     if (rc) return rc;
-    if (b->desc.precision != GSCL_PREC_F64) {
+    if (b->desc.method == GSCL_BATCH_JACOBI && b->desc.precision != GSCL_PREC_F64) {
         gk::Geo g = geo_of(u);
         GSCL_HIP(gk::launch_fill(s.d, GSCL_F32, 0.0, g, c->stream));
     }
@@ -476,7 +507,15 @@ static int enqueue_step(gscl_batch* b) {
     const double rtol2 = b->desc.rtol * b->desc.rtol;
     const dim3 grid(b->persist_blocks), blk(64 * BNW);
     const int ms = b->desc.max_slots;
-    if (b->desc.precision == GSCL_PREC_F64) {
+    if (b->desc.method == GSCL_BATCH_RBGS) {
+        for (int k = 0; k < 2 * S; ++k)
+            hipLaunchKernelGGL((batch_sweep<MODE_RBGS, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                               b->d_partials, k & 1, 0.0);
+        hipLaunchKernelGGL((batch_sweep<MODE_RESID, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                           b->d_partials, 0, 0.0);
+        hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
+                           rtol2, S, (long long)b->desc.max_sweeps, 0);
+    } else if (b->desc.precision == GSCL_PREC_F64) {
         for (int k = 1; k <= S; ++k) {
             const int parity = (k - 1) & 1;
             if (k < S)

@@ -69,12 +69,12 @@ class SolveServer:
     def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
                  rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
                  hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7,
-                 pipelined: bool = True):
+                 pipelined: bool = True, method: int = G.BATCH_JACOBI):
         self.ctx = ctx
         self.pipelined = pipelined
         self.batch = G.Batch(ctx, max_slots=max_slots, precision=precision,
                              sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,
-                             rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps)
+                             rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps, method=method)
 
     def _admit(self, job: Job, now: float) -> bool:
         shape = (job.n, job.n, job.n)
@@ -135,8 +135,9 @@ class SolveServer:
 
 def serve_sequential(ctx: G.Context, jobs: list[Job], rtol: float = 1e-8, omega: float = 6 / 7,
                      check_every: int = 64, precision: int = G.PREC_F64, inner_sweeps: int = 64,
-                     realtime: bool = True) -> ServeReport:
-    """One solve at a time with gscl_solve (the plain path), same queueing rules."""
+                     realtime: bool = True, kind: int = G.K_WJACOBI) -> ServeReport:
+    """One solve at a time with gscl_solve (the plain path), same queueing rules.
+    kind K_WJACOBI or K_RBGS (red-black SOR, omega = 0 for the optimal weight)."""
     t0 = time.perf_counter()
     for job in sorted(jobs, key=lambda j: j.arrival):
         now = time.perf_counter() - t0
@@ -147,7 +148,7 @@ def serve_sequential(ctx: G.Context, jobs: list[Job], rtol: float = 1e-8, omega:
         job.u.fill(0.0)
         job.fg = job.f if isinstance(job.f, G.Grid) else ctx.grid(shape, G.F64, halo=0, data=job.f)
         job.admitted_at = time.perf_counter() - t0
-        st = ctx.solve(G.K_WJACOBI, [job.u], [job.fg], omega=omega, h2=job.h2, rtol=rtol,
+        st = ctx.solve(kind, [job.u], [job.fg], omega=omega, h2=job.h2, rtol=rtol,
                        check_every=check_every, precision=precision, inner_sweeps=inner_sweeps)
         job.done_at = time.perf_counter() - t0
         job.sweeps, job.rel_residual, job.state = st["sweeps"], st["rel_residual"], 2

@@ -99,3 +99,38 @@ def test_begin_without_gpu_reports_hip_error():
     assert L.gscl_begin(h, None) == G.ERR_HIP
     assert b"hip" in L.gscl_last_error().lower()
     L.gscl_finalize(h)
+
+
+_STRUCTS = {
+    "gscl_grid_desc": G.GridDesc, "gscl_term": G.Term, "gscl_stencil_desc": G.StencilDesc,
+    "gscl_reduce_desc": G.ReduceDesc, "gscl_tile": G.Tile, "gscl_solve_desc": G.SolveDesc,
+    "gscl_solve_stats": G.SolveStats, "gscl_batch_desc": G.BatchDesc, "gscl_slot_stats": G.SlotStats,
+}
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every descriptor the binding passes by pointer has the size and field
+    offsets the C compiler gives the header's struct (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "gscl.h"', "int main(void) {"]
+    for cname, py in _STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, what, val = line.split()
+        got[(cname, what)] = int(val)
+    for cname, py in _STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

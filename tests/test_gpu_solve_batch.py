@@ -114,10 +114,11 @@ def test_vc13_solve_per_precision(ctx, prec, dt):
         assert np.abs(gx[f].numpy() - xo).max() <= 1e-9 * 10 * np.abs(xo).max()
 
 
-def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8):
+def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8, method=G.BATCH_JACOBI,
+                 omega=6 / 7):
     """Run requests through one batch; admit_at[i] = step index to admit request i."""
     b = G.Batch(ctx, max_slots=8, precision=prec, sweeps_per_step=S, use_graph=use_graph, rtol=rtol,
-                hbm_budget=1 << 30)
+                hbm_budget=1 << 30, method=method, omega=omega)
     admit_at = admit_at or [0] * len(reqs)
     grids = {}
     out = {}
@@ -173,6 +174,50 @@ def test_batch_f64_matches_solver_and_oracle(sctx):
         gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
         st = ctx.solve(G.K_WJACOBI, [u], [gf], h2=r.h2, rtol=1e-8, check_every=S)
         assert st["sweeps"] == so and np.array_equal(u.numpy(), res[i][0])
+
+
+@pytest.mark.parametrize("omega", [0.0, 1.0, 1.7])
+def test_batch_rbgs_matches_solver_and_oracle(sctx, omega):
+    """Red-black SOR slots: alone == among others (bitwise), and the same
+    stopping sweep and iterate as the plain checked solve and the oracle."""
+    ctx = sctx
+    reqs = [_req(n, seed=n + 2, rid=i) for i, n in enumerate((21, 34, 16))]
+    S = 4
+    mix = _batch_solve(ctx, reqs, G.PREC_F64, S, admit_at=[0, 1, 2], method=G.BATCH_RBGS, omega=omega)
+    for i, r in enumerate(reqs):
+        _, f = W.poisson_fields(r)
+        alone = _batch_solve(ctx, [r], G.PREC_F64, S, use_graph=False, method=G.BATCH_RBGS, omega=omega)[0]
+        assert np.array_equal(alone[0], mix[i][0]), i
+        assert alone[1]["sweeps"] == mix[i][1]["sweeps"] and mix[i][1]["state"] == 2
+        u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+        gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+        st = ctx.solve(G.K_RBGS, [u], [gf], omega=omega, h2=r.h2, rtol=1e-8, check_every=S)
+        assert st["sweeps"] == mix[i][1]["sweeps"] and np.array_equal(u.numpy(), mix[i][0])
+        w = omega
+        if w == 0.0:
+            c = math.cos(math.pi / (r.n + 1))
+            rho = (c + c + c) / 3.0
+            w = 2 / (1 + math.sqrt(1 - rho * rho))
+        uo, so, _, conv = oracle.rbgs_solve(f, r.h2, w, 1e-8, S, 10 ** 6)
+        assert conv and mix[i][1]["sweeps"] == so
+        assert np.abs(mix[i][0] - uo).max() <= 1e-11 * np.abs(uo).max()
+        assert _oracle_rel_residual(mix[i][0], f, r.h2) <= 1e-8 * 1.01
+
+
+def test_batch_rbgs_errors_and_footprint(ctx):
+    with pytest.raises(G.GsclError) as e:
+        G.Batch(ctx, precision=G.PREC_F32_IR, method=G.BATCH_RBGS)
+    assert e.value.code == G.ERR_UNSUPPORTED
+    for kw in ({"omega": 2.0}, {"omega": -0.5}, {"method": 2}):
+        with pytest.raises(G.GsclError) as e:
+            G.Batch(ctx, **{"method": G.BATCH_RBGS, **kw})
+        assert e.value.code == G.ERR_ARG
+    jb = G.Batch(ctx, max_slots=1, hbm_budget=1 << 20)
+    rb = G.Batch(ctx, max_slots=1, hbm_budget=1 << 20, method=G.BATCH_RBGS, omega=0.0)
+    # in-place sweeps: the work grid is one F32 residual instead of an F64 ping-pong grid
+    assert rb.footprint((40, 40, 40)) < jb.footprint((40, 40, 40))
+    jb.close()
+    rb.close()
 
 
 def test_batch_budget_admission(ctx):
