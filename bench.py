@@ -40,6 +40,7 @@ KERNEL_SOURCES = {
     "reduce_f64": [_CS + f for f in ("kcommon.h", "k_reduce.hip")],
     "wjacobi_tb_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "tb7.h", "k_sweep_tb.hip")],
     "rbgs_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "sweeps_common.h", "k_sweep_wjacobi.hip")],
+    "rbgs_tb_512": [_CS + f for f in ("kcommon.h", "tiled.h", "ops.h", "tb7.h", "k_sweep_tb.hip")],
     "tridiag_512": [_CS + f for f in ("kcommon.h", "launch.h", "k_line.hip")],
     "vc13_512": [_CS + f for f in ("kcommon.h", "tiled.h", "zq13.h", "ops.h", "sweeps_common.h",
                                   "k_sweep_vc13a.hip")],
@@ -372,6 +373,103 @@ class RBGS:
                 "sample": f"{reps} red-black FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
 
 
+class RBGSTB:
+    """Red-black SOR (omega 1.9) on a 512^3 FP64 cube with a right-hand side,
+    Dirichlet 0: 8 sweeps per step as four blocked passes of 4 colour passes
+    (2 sweeps each, the last with the fused L2 norm of its update).  The same
+    sweeps as in-place colour passes are timed beside it (the same grid, bit
+    for bit), and one N = 192 Poisson request is solved by optimal SOR (its
+    chunks run as blocked passes)."""
+    key = "rbgs_tb_512"
+    bytes_per_point = 24  # per blocked pass: u and f read once, the 4-pass result written once
+
+    def __init__(self, ctx, n=512, sweeps=8, k=4):
+        import torch
+        import paper_1207_1746_amd as G
+        from paper_1207_1746_amd import workloads as W
+        self.G, self.W = G, W
+        self.n, self.sweeps, self.k = n, sweeps, k
+        u0, self.h2 = W.jacobi_cube(n)
+        f = W.jacobi_rhs(n)
+        self.host = (u0, f)
+        self.a = ctx.grid(u0.shape, G.F64, halo=1, data=u0)
+        self.b = ctx.grid(u0.shape, G.F64, halo=1)
+        self.f = ctx.grid(u0.shape, G.F64, halo=0, data=f)
+        self.res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.ctx = ctx
+        self.points = n ** 3
+        self.units_per_step = self.points * sweeps
+        self.unit = "Gpts/s"
+        self.omega = 1.9
+        self.extra = {}
+
+    def step(self, ev=None):
+        G = self.G
+        passes = 2 * self.sweeps // self.k
+        for q in range(passes):
+            src, dst = (self.a, self.b) if q % 2 == 0 else (self.b, self.a)
+            last = q == passes - 1
+            if ev is not None and not last:
+                ev.begin()
+            self.ctx.do_all(G.K_RBGS_TB, [src, self.f], [dst], p=(self.omega, self.h2, (q * self.k) % 2, self.k),
+                            reduce=(G.R_L2, G.RV_UPDATE) if last else None,
+                            dev_result=self.res if last else None)
+            if ev is not None and not last:
+                ev.end()
+
+    def _inplace(self):
+        G = self.G
+        for q in range(2 * self.sweeps):
+            self.ctx.do_all(G.K_RBGS, [self.a, self.f], [self.a], p=(self.omega, self.h2, q % 2))
+
+    def after(self):
+        import torch
+        G, W = self.G, self.W
+        self._inplace()
+        sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            self._inplace()
+        b.record()
+        sync()
+        ms = a.elapsed_time(b) / reps
+        req = W.poisson_requests(count=1, qps=float("inf"), nmin=192, nmax=192, seed_index=7)[0]
+        _, f = W.poisson_fields(req)
+        gf = self.ctx.grid(f.shape, G.F64, halo=0, data=f)
+        u = self.ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+        t0 = time.perf_counter()
+        st = self.ctx.solve(G.K_RBGS, [u], [gf], omega=0.0, h2=req.h2, rtol=1e-8, check_every=16)
+        sec = time.perf_counter() - t0
+        self.extra = {"inplace_colour_passes": {"ms_per_step": round(ms, 3),
+                                                "Gpts_s": round(self.units_per_step / ms / 1e6, 2)},
+                      "colour_passes_per_blocked_pass": self.k,
+                      "poisson_192_sor_to_1e-8": {"sweeps": st["sweeps"], "seconds": round(sec, 4),
+                                                  "rel_residual": st["rel_residual"]}}
+
+    def config(self):
+        return {"workload": f"red-black SOR (omega {self.omega}) 7-point {self.n}^3 FP64 with right-hand side, "
+                            f"Dirichlet 0, {self.sweeps} sweeps per step as blocked passes of {self.k} colour "
+                            f"passes + L2 of the last update", "grid": [self.n] * 3}
+
+    def cpu_baseline(self, budget_s=10.0):
+        import oracle
+        u0, f = self.host
+        t0 = time.perf_counter()
+        reps = 0
+        u = u0
+        while True:
+            u = oracle.rbgs_sweep(u, f, self.omega, self.h2)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(self.points * reps / dt / 1e9, 4), "unit": self.unit,
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{reps} red-black FP64 sweeps of the 512^3 workload in {dt:.1f} s"}
+
+
 class Tridiag:
     """Ordered line iteration spaces: tridiagonal solves along k (do_k_inc
     elimination, do_k_dec substitution) for every column of a 512^3 FP64
@@ -667,7 +765,8 @@ class VC13:
                 "sample": f"{reps} single-field FP64 applies in {dt:.1f} s (scaled to 5 fields)"}
 
 
-WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs": RBGS, "tridiag": Tridiag,
+WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs": RBGS, "rbgs_tb": RBGSTB,
+             "tridiag": Tridiag,
              "image": Image,
              "serve": Serve, "reduce": Reduce,
              "vc13": VC13}
@@ -794,7 +893,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "rbgs": "f64", "tridiag": "f64",
+        "dtype": {"varcoef": "f32", "jacobi": "f64", "jacobi_tb": "f64", "rbgs": "f64", "rbgs_tb": "f64",
+                  "tridiag": "f64",
                   "image": "u8", "reduce": "f64",
                   "vc13": "bf16"}[args.config],
         "data": "synthetic (seeded)",

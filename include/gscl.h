@@ -151,6 +151,14 @@ typedef struct gscl_batch gscl_batch;
  *   the others keep their value.  ndim 3, F64 or F32, Dirichlet rule.  Fused
  *   operands cover the pass's points (UPDATE = u' - u, RESIDUAL before the
  *   update), 0 elsewhere.  Tiles as GSCL_K_WJACOBI.
+ * GSCL_K_RBGS_TB (Sections 2 and 3: wide ghost areas over red-black passes):
+ *   k successive GSCL_K_RBGS colour passes, alternating colours from p[2],
+ *   in one pass over memory, out of place.  in = {u} or {u, f}; out = {u
+ *   after the k passes}, which may not overlap u or f; p[0] = omega,
+ *   p[1] = h^2, p[2] = first colour, p[3] = k in 1..4 (k = 2m: m full
+ *   red-black sweeps).  ndim 3, F64 or F32, Dirichlet rule.  The result is
+ *   bitwise the one k in-place passes give; fused operands refer to the last
+ *   pass.  Tiles as GSCL_K_WJACOBI_TB.
  *
  * Operators of the ordered line iteration spaces (gscl_do_line below).  The
  * value the operator wrote at the previously processed cell of a line is
@@ -188,7 +196,8 @@ enum {
     GSCL_K_TRIDIAG_FWD = 11,
     GSCL_K_TRIDIAG_BACK = 12,
     GSCL_K_DIAMOND_RECUR = 13,
-    GSCL_K_GS2D = 14
+    GSCL_K_GS2D = 14,
+    GSCL_K_RBGS_TB = 15
 };
 
 typedef struct {
@@ -301,8 +310,9 @@ int gscl_do_reduce(gscl_ctx *ctx, const gscl_reduce_desc *rd, const gscl_grid *a
  * {1,2} with FP32 math, 1 with FP64 math; F64 {1,2}), NW in {4,8} (radius-2
  * kinds: 4 for one field, {4,6,8} for five fields), cz >= 1.  A shape with no
  * kernel for the kind is reported by the launch as GSCL_ERR_UNSUPPORTED.
- * GSCL_K_WJACOBI_TB has a fixed block shape (V = 1, NW = 16, two rows per
- * wave): gscl_tile_set takes only its cz and gscl_tile_get reports it so. */
+ * GSCL_K_WJACOBI_TB and GSCL_K_RBGS_TB have a fixed block shape (V = 1,
+ * NW = 16, two rows per wave): gscl_tile_set takes only their cz and
+ * gscl_tile_get reports it so. */
 typedef struct { int32_t V, NW, cz; } gscl_tile;
 int gscl_tile_get(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, gscl_tile *out);
 int gscl_tile_set(gscl_ctx *ctx, int kind, const gscl_grid_desc *grid, const gscl_tile *tile);
@@ -331,8 +341,11 @@ typedef struct {
     int32_t inner_sweeps;       /* IR: low-precision sweeps per outer step */
     int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f),
                                    GSCL_K_RBGS (Poisson by red-black Gauss-Seidel /
-                                   SOR, F64, in place; the check follows each chunk
-                                   as a separate residual pass), or
+                                   SOR, F64: colour passes in place, or on grids of
+                                   144^3 points or more GSCL_K_RBGS_TB passes of up
+                                   to 4 colour passes through a workspace grid; the
+                                   check follows each chunk as a separate residual
+                                   pass), or
                                    GSCL_K_VC13_APPLY (A x = b, several fields) */
     int64_t max_sweeps;
 } gscl_solve_desc;

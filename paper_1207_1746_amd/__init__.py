@@ -27,7 +27,7 @@ F64, F32, F16, BF16, U8, I16, U32 = range(7)
 DIRICHLET, PERIODIC, CLAMP = 0, 1, 2
 K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_VC13_RESID, \
     K_POISSON_RESID, K_WJACOBI_TB, K_RBGS, K_LINE_RECUR, K_TRIDIAG_FWD, K_TRIDIAG_BACK, \
-    K_DIAMOND_RECUR, K_GS2D = range(15)
+    K_DIAMOND_RECUR, K_GS2D, K_RBGS_TB = range(16)
 R_SUM, R_SUMSQ, R_L2, R_MAXABS, R_ALL_LE = range(5)
 RV_OUT0, RV_UPDATE, RV_RESIDUAL = range(3)
 PREC_F64, PREC_F32_IR, PREC_BF16_IR, PREC_F16_IR = range(4)

@@ -210,7 +210,7 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
     if (it != c->tiles.end()) return it->second;
     gk::TileCfg t;
     const int64_t nx = d.n[0];
-    if (kind == GSCL_K_WJACOBI_TB) {
+    if (kind == GSCL_K_WJACOBI_TB || kind == GSCL_K_RBGS_TB) {
         // output planes per block (measured on MI355X from 64^3 to 512^3): the
         // largest power of two up to (output tiles per plane) * nz / 160,
         // within 1..64 -- long enough to amortize the 2k warm-up planes, short
@@ -267,7 +267,7 @@ static gk::TileCfg reduce_tile(gk::TileCfg t, const gscl_grid_desc& d) {
 extern "C" int gscl_tile_set(gscl_ctx* c, int kind, const gscl_grid_desc* gd, const gscl_tile* t) {
     if (!ctx_ok(c) || !gd || !t) return gscl_fail(GSCL_ERR_ARG, "invalid argument");
     // the temporally blocked kind has a fixed block shape: only cz applies
-    const bool shape_fixed = kind == GSCL_K_WJACOBI_TB;
+    const bool shape_fixed = kind == GSCL_K_WJACOBI_TB || kind == GSCL_K_RBGS_TB;
     if (!shape_fixed && t->V != 1 && t->V != 2 && t->V != 4) return gscl_fail(GSCL_ERR_ARG, "V must be 1, 2 or 4");
     if (!shape_fixed && t->NW != 4 && t->NW != 6 && t->NW != 8)
         return gscl_fail(GSCL_ERR_ARG, "NW must be 4, 6 or 8");
@@ -553,6 +553,40 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
                 fill_red(c, fused, ta.ra);
             }
             he = gk::launch_wjacobi_tb(ta, dt == GSCL_F64 ? 0 : 1, n_in == 2, red, c->stream, &nblocks);
+            break;
+        }
+        case GSCL_K_RBGS_TB: {
+            if (n_in < 1 || n_in > 2 || n_out != 1) return gscl_fail(GSCL_ERR_ARG, "RBGS_TB takes {u[, f]} -> {u_k}");
+            if (dt != GSCL_F64 && dt != GSCL_F32) return gscl_fail(GSCL_ERR_DTYPE, "RBGS_TB needs F64 or F32 grids");
+            if ((rc = check_dtypes(in, 0, n_in, dt, "input")) || (rc = check_dtypes(out, 0, n_out, dt, "output")))
+                return rc;
+            if ((rc = check_nb(in, 0, 1, 1, out, n_out, 3))) return rc;
+            if (n_in == 2 && overlaps(in[1], out[0]))
+                return gscl_fail(GSCL_ERR_ALIAS, "RBGS_TB output aliases the right-hand side");
+            if (g0->d.bc != GSCL_BC_DIRICHLET) return gscl_fail(GSCL_ERR_UNSUPPORTED, "RBGS_TB uses the Dirichlet rule");
+            if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "RBGS_TB needs h^2 != 0 in p[1]");
+            if (op->p[2] != 0.0 && op->p[2] != 1.0) return gscl_fail(GSCL_ERR_ARG, "RBGS_TB first colour p[2] must be 0 or 1");
+            const double kd = op->p[3];
+            if (!(kd >= 1.0 && kd <= (double)gk::TB_KMAX) || kd != (double)(int)kd)
+                return gscl_fail(GSCL_ERR_ARG, "RBGS_TB needs k = p[3] in 1..%d", gk::TB_KMAX);
+            gk::TBArgs ta{};
+            ta.g = geo_of(g0);
+            ta.u = in[0]->ptr;
+            ta.f = n_in == 2 ? in[1]->ptr : nullptr;
+            ta.out = out[0]->ptr;
+            ta.p[0] = op->p[0];
+            ta.p[1] = op->p[1];
+            ta.p[2] = 1.0 / op->p[1];
+            ta.p[3] = op->p[2];
+            ta.k = (int)kd;
+            ta.operand = red ? fused->operand : 0;
+            gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
+            ta.cz = t.cz;
+            if (red) {
+                if ((rc = ensure_partials(c, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
+                fill_red(c, fused, ta.ra);
+            }
+            he = gk::launch_rbgs_tb(ta, dt == GSCL_F64 ? 0 : 1, n_in == 2, red, c->stream, &nblocks);
             break;
         }
         case GSCL_K_POISSON_RESID: {

@@ -1,10 +1,11 @@
-// Temporally blocked weighted-Jacobi instantiations (k sweeps per pass).
+// Temporally blocked instantiations: weighted Jacobi (k sweeps per pass) and
+// red-black relaxation (k colour passes per pass).
 #include "launch.h"
 #include "tb7.h"
 
 namespace gk {
 
-template <class T, bool HAS_F, int KMAX>
+template <class T, bool HAS_F, int KMAX, bool RB>
 static hipError_t run_tb(TBArgs& a, bool red, hipStream_t s, int* nblocks) {
     const int ox = 64 - 2 * a.k, oy = TB_ROWS - 2 * a.k;
     a.ntx = (a.g.nx + ox - 1) / ox;
@@ -14,12 +15,12 @@ static hipError_t run_tb(TBArgs& a, bool red, hipStream_t s, int* nblocks) {
     *nblocks = n;
     if (n == 0) return hipSuccess;
     if (red) {
-        hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, true>), dim3(n), dim3(64 * TB_NW), 0, s, a);
+        hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, true, RB>), dim3(n), dim3(64 * TB_NW), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_reduce_finish(a.ra, n, s);
     }
-    hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, false>), dim3(n), dim3(64 * TB_NW), 0, s, a);
+    hipLaunchKernelGGL((tb7_sweep<T, HAS_F, KMAX, false, RB>), dim3(n), dim3(64 * TB_NW), 0, s, a);
     return hipGetLastError();
 }
 
@@ -28,13 +29,25 @@ int tb_blocks(const Geo& g, int k, int cz) {
     return ((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * ((g.nz + cz - 1) / cz);
 }
 
-hipError_t launch_wjacobi_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nb) {
+template <bool RB>
+static hipError_t dispatch_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nb) {
     if (a.k < 1 || a.k > TB_KMAX) return hipErrorInvalidValue;
     if (dtype == 0)
-        return has_f ? run_tb<double, true, TB_KMAX>(a, red, s, nb) : run_tb<double, false, TB_KMAX>(a, red, s, nb);
+        return has_f ? run_tb<double, true, TB_KMAX, RB>(a, red, s, nb)
+                     : run_tb<double, false, TB_KMAX, RB>(a, red, s, nb);
     if (dtype == 1)
-        return has_f ? run_tb<float, true, TB_KMAX>(a, red, s, nb) : run_tb<float, false, TB_KMAX>(a, red, s, nb);
+        return has_f ? run_tb<float, true, TB_KMAX, RB>(a, red, s, nb)
+                     : run_tb<float, false, TB_KMAX, RB>(a, red, s, nb);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_wjacobi_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nb) {
+    return dispatch_tb<false>(a, dtype, has_f, red, s, nb);
+}
+
+hipError_t launch_rbgs_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nb) {
+    if (a.g.bc != BC_DIRICHLET) return hipErrorInvalidValue;
+    return dispatch_tb<true>(a, dtype, has_f, red, s, nb);
 }
 
 }  // namespace gk

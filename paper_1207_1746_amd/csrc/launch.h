@@ -69,6 +69,8 @@ hipError_t launch_diamond(DiamondArgs& a, int dtype, int kind, hipStream_t s);
 struct TBArgs;
 constexpr int TB_KMAX = 4;
 hipError_t launch_wjacobi_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nblocks);
+// k red-black colour passes per pass (first colour in a.p[3]), Dirichlet rule only.
+hipError_t launch_rbgs_tb(TBArgs& a, int dtype, bool has_f, bool red, hipStream_t s, int* nblocks);
 int tb_blocks(const Geo& g, int k, int cz);
 
 // Generic linear operator (any offsets, per-grid boundary rule).

@@ -27,6 +27,24 @@ struct TmpGrid {
 
 size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Poisson chunks on grids of at least 144^3 points run temporally blocked
+// passes (measured faster from there on).
+bool blocked_passes(const gscl_grid_desc& d) { return d.n[0] * d.n[1] * d.n[2] >= (int64_t)144 * 144 * 144; }
+
+// Split n sweeps (or colour passes) into passes of at most TB_KMAX, with an
+// even pass count so that a ping-pong chunk ends in the caller's grid.
+std::vector<int> split_passes(int n) {
+    std::vector<int> passes;
+    for (int left = n; left > 0; left -= passes.back()) passes.push_back(std::min(left, gk::TB_KMAX));
+    if (passes.size() % 2) {
+        const int last = passes.back();
+        passes.pop_back();
+        passes.push_back(last - last / 2);
+        passes.push_back(last / 2);
+    }
+    return passes;
+}
+
 size_t bytes_like(const gscl_grid_desc& d, int dtype) {
     return round256((size_t)d.pitch[1] * (size_t)std::max<int64_t>(d.n[2], 1) * dtype_size(dtype));
 }
@@ -79,7 +97,8 @@ struct Cleanup {
 extern "C" size_t gscl_solve_workspace_bytes(const gscl_solve_desc* sd, const gscl_grid* x, int nf) {
     if (!sd || !grid_ok(x) || nf < 1) return 0;
     const gscl_grid_desc& d = x->d;
-    if (sd->kind == GSCL_K_RBGS) return bytes_like(d, GSCL_F32) + 256;  // residual grid
+    if (sd->kind == GSCL_K_RBGS)  // residual grid, and the ping-pong grid of blocked passes
+        return bytes_like(d, GSCL_F32) + (blocked_passes(d) ? bytes_like(d, GSCL_F64) : 0) + 256;
     if (sd->precision == GSCL_PREC_F64) return bytes_like(d, GSCL_F64) * nf + 256;
     const int s = inner_dtype(sd->precision);
     if (sd->kind == GSCL_K_WJACOBI) return bytes_like(d, GSCL_F32) * 3 + 256;
@@ -178,9 +197,12 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
     };
 
     if (rbgs) {
-        // Red-black relaxation in place: a chunk is S sweeps (a red and a
-        // black pass each) and then the residual of the current x, so the
-        // grid returned is the grid that was checked.  omega = 0 selects the
+        // Red-black relaxation: a chunk is S sweeps (a red and a black pass
+        // each) and then the residual of the current x, so the grid returned
+        // is the grid that was checked.  On large grids the 2S colour passes
+        // run as blocked passes of up to TB_KMAX colour passes, ping-ponging
+        // through a workspace grid (an even count, so the chunk ends in x);
+        // elsewhere each colour pass runs in place.  omega = 0 selects the
         // optimal SOR weight of the model problem, 2 / (1 + sqrt(1 - rho^2)),
         // rho = (cos(pi/(nx+1)) + cos(pi/(ny+1)) + cos(pi/(nz+1))) / 3 the
         // Jacobi spectral radius for a uniform grid spacing.
@@ -192,16 +214,30 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
         }
         gscl_grid* r = carve(c, xd, GSCL_F32, 0, cur, cl.grids);
         const int S = sd->check_every;
+        const bool tb = blocked_passes(xd);
+        gscl_grid* w = tb ? carve(c, xd, GSCL_F64, 1, cur, cl.grids) : nullptr;
+        const std::vector<int> passes = tb ? split_passes(2 * S) : std::vector<int>(2 * S, 1);
         if ((rc = gscl_graph_begin(c))) return rc;
-        for (int k = 0; k < 2 * S && rc == GSCL_OK; ++k) {
+        int colour = 0;
+        for (size_t q = 0; q < passes.size() && rc == GSCL_OK; ++q) {
             gscl_stencil_desc op;
             memset(&op, 0, sizeof op);
-            op.kind = GSCL_K_RBGS;
             op.p[0] = omega;
             op.p[1] = sd->h2;
-            op.p[2] = k % 2;
-            gscl_grid* in[2] = {x[0], const_cast<gscl_grid*>(b[0])};
-            rc = gscl_do_all(c, &op, in, 2, x, 1, nullptr, nullptr);
+            op.p[2] = colour;
+            gscl_grid* src = x[0];
+            gscl_grid* dst = x[0];
+            if (tb) {
+                op.kind = GSCL_K_RBGS_TB;
+                op.p[3] = passes[q];
+                src = q % 2 == 0 ? x[0] : w;
+                dst = q % 2 == 0 ? w : x[0];
+            } else {
+                op.kind = GSCL_K_RBGS;
+            }
+            gscl_grid* in[2] = {src, const_cast<gscl_grid*>(b[0])};
+            rc = gscl_do_all(c, &op, in, 2, &dst, 1, nullptr, nullptr);
+            colour = (colour + passes[q]) & 1;
         }
         if (rc == GSCL_OK) {
             gscl_stencil_desc op;
@@ -238,19 +274,8 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
         // chunks on large grids run temporally blocked passes of up to TB_KMAX
         // sweeps (the same sweeps bit for bit, fewer passes); elsewhere every
         // pass is one sweep.  The pass count is kept even so the chunk ends in x.
-        const bool tb = poisson && xd.n[0] * xd.n[1] * xd.n[2] >= (int64_t)144 * 144 * 144;
-        std::vector<int> passes;
-        if (tb) {
-            for (int left = S; left > 0; left -= passes.back()) passes.push_back(std::min(left, gk::TB_KMAX));
-            if (passes.size() % 2) {
-                const int last = passes.back();
-                passes.pop_back();
-                passes.push_back(last - last / 2);
-                passes.push_back(last / 2);
-            }
-        } else {
-            passes.assign(S, 1);
-        }
+        const bool tb = poisson && blocked_passes(xd);
+        const std::vector<int> passes = tb ? split_passes(S) : std::vector<int>(S, 1);
         // capture one chunk: x -> w -> x ...
         if ((rc = gscl_graph_begin(c))) return rc;
         for (size_t q = 0; q < passes.size() && rc == GSCL_OK; ++q) {

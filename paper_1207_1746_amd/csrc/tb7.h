@@ -1,5 +1,6 @@
-// Temporal blocking for the 7-point weighted Jacobi sweep: k sweeps per pass
-// over HBM (wide ghost zones).
+// Temporal blocking for the 7-point weighted Jacobi sweep and for red-black
+// relaxation: k sweeps (or k colour passes) per pass over HBM (wide ghost
+// zones).
 //
 // A block of 16 waves owns a working region of 64 columns x 32 rows (two rows
 // per wave) and marches it through z.  The region is the output tile grown
@@ -10,16 +11,28 @@
 // At march step s the block loads input plane s (level 0) and computes, for
 // t = 1..k, level t at plane s - t: its z neighbours are the thread's own
 // level t-1 values at planes s-t-1, s-t (registers) and s-t+1 (computed
-// earlier in the same step), its x/y neighbours come from level t-1 of
-// plane s-t staged in LDS at the start of the step.  Each thread therefore
-// holds two planes per level plus the right-hand side of the k planes in
-// flight, and every input plane is read from HBM once per k sweeps.
+// earlier in the same step).  A wave holds whole rows (one column per lane),
+// so x neighbours come from the adjacent lanes by wave-wide DPP shifts and
+// the y neighbour inside the wave's own rows from a register; only the row
+// of the next wave up or down goes through LDS, where every wave stages its
+// level t-1 rows at the start of the step.  Each thread therefore holds two
+// planes per level plus the right-hand side of the k planes in flight, and
+// every input plane is read from HBM once per k sweeps.
 //
 // Outside the domain, levels take the Dirichlet value; under the periodic
 // rule the loads wrap and the computed values are the periodic extension.
 // The per-point arithmetic is the plain sweep's operator, so the result is
 // the one k separate sweeps produce, bit for bit.
+//
+// Red-black levels (RB): level t is one colour pass of level t-1, colour
+// (c0 + t - 1) mod 2 with c0 = p[3], using the in-place pass's operator.  An
+// in-place colour pass reads only points of the other colour, which it does
+// not change, so it equals the same pass computed out of place; k levels are
+// therefore k in-place passes, bit for bit, and a pass of 2m levels is m
+// full red-black sweeps.
 #pragma once
+
+#include <type_traits>
 
 #include "ops.h"
 
@@ -30,8 +43,8 @@ struct TBArgs {
     const void* u;    // input grid (level 0)
     const void* f;    // right-hand side (may be null)
     void* out;        // level k
-    double p[8];      // operator parameters of the plain sweep
-    int k;            // sweeps per pass, 1..KMAX
+    double p[8];      // operator parameters of the plain sweep (RB: p[3] = first colour)
+    int k;            // sweeps (colour passes) per pass, 1..KMAX
     int ntx, nty, ncz, cz;
     int operand;
     RedArgs ra;
@@ -39,11 +52,29 @@ struct TBArgs {
 
 constexpr int TB_NW = 16, TB_RPW = 2, TB_ROWS = TB_NW * TB_RPW;
 
-template <class T, bool HAS_F, int KMAX, bool RED>
+// Value of the lane below (lane - 1) or above (lane + 1) in the wave, by
+// wave-wide DPP shifts (wave_shr:1 / wave_shl:1); lanes without a source get 0.
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
+
+template <class T, bool HAS_F, int KMAX, bool RED, bool RB>
 __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
-    using Op = OpWJacobi<T, T, 3, HAS_F>;
-    constexpr int R = TB_RPW, W = 64 + 2, H = TB_ROWS + 2;
-    __shared__ T lds[KMAX][H][W];
+    using Op = typename std::conditional<RB, OpRBGS<T, HAS_F>, OpWJacobi<T, T, 3, HAS_F>>::type;
+    constexpr int R = TB_RPW;
+    // the rows every wave stages per level, in two copies alternating by
+    // step: a step's staging writes the copy the previous step did not read,
+    // so one barrier per step suffices (FP64: 128 KB, one block per CU)
+    __shared__ T lds[2][KMAX][TB_NW][R][64];
 
     const Geo& g = a.g;
     const int k = a.k;
@@ -51,6 +82,9 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
     const int ntiles = a.ntx * a.nty * a.ncz;
     const int tile = xcd_remap(blockIdx.x, ntiles);
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // waves whose rows border this wave's (the block's edge waves read their
+    // own rows there: those rows lie in the ghost zone, never written)
+    const int wdn = w > 0 ? w - 1 : 0, wup = w < TB_NW - 1 ? w + 1 : TB_NW - 1;
     const int xt = tile % a.ntx, rest = tile / a.ntx, yt = rest % a.nty, zc = rest / a.nty;
     const int z0 = zc * a.cz, z1 = min(z0 + a.cz, g.nz);
     const int x = xt * ox - k + lane;
@@ -60,12 +94,13 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
     const bool x_out = lane >= k && lane < 64 - k && x_in;
     const T bcv = (T)g.bcv;
 
-    int row[R], ys[R];
+    int row[R], ys[R], yg[R];
     bool y_in[R], y_out[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         row[i] = w * R + i;
         const int y = yt * oy - k + row[i];
+        yg[i] = y;
         y_in[i] = (unsigned)y < (unsigned)g.ny;
         ys[i] = y_in[i] ? y : wrap_idx(y, g.ny, dir ? BC_CLAMP : g.bc);
         y_out[i] = row[i] >= k && row[i] < TB_ROWS - k && y_in[i];
@@ -129,11 +164,12 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
             }
         }
         // stage level t-1 of plane s-t for every level t
+        T(*lb)[TB_NW][R][64] = lds[(s - s_begin) & 1];
 #pragma unroll
         for (int t = 1; t <= KMAX; ++t) {
             if (t > k) break;
 #pragma unroll
-            for (int i = 0; i < R; ++i) lds[t - 1][row[i] + 1][lane + 1] = hist[t - 1][i][1];
+            for (int i = 0; i < R; ++i) lb[t - 1][w][i][lane] = hist[t - 1][i][1];
         }
         __syncthreads();
         // newest value of the level below, per row
@@ -145,21 +181,30 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
             if (t > k) break;
             const int zp = s - t;
             const bool z_in = (unsigned)zp < (unsigned)g.nz;
+            // red-black: this level's colour in p[3]
+            const double pl[4] = {a.p[0], a.p[1], a.p[2], (double)(((int)a.p[3] + t - 1) & 1)};
+            const double* pt = RB ? pl : a.p;
+            // level t-1 of plane s-t, this wave's rows
+            T cc[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) cc[i] = hist[t - 1][i][1];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 Star<T, 1, 1> st;
-                st.c[0] = hist[t - 1][i][1];
+                st.c[0] = cc[i];
                 st.zm[0][0] = hist[t - 1][i][0];
                 st.zp[0][0] = below[i];
-                const int r1 = row[i] + 1;
-                st.xm[0][0] = lds[t - 1][r1][lane];
-                st.xp[0][0] = lds[t - 1][r1][lane + 2];
-                st.ym[0][0] = lds[t - 1][r1 - 1][lane + 1];
-                st.yp[0][0] = lds[t - 1][r1 + 1][lane + 1];
+                st.xm[0][0] = lane_shift<DPP_WAVE_SHR1>(cc[i]);
+                st.xp[0][0] = lane_shift<DPP_WAVE_SHL1>(cc[i]);
+                st.ym[0][0] = i > 0 ? cc[i > 0 ? i - 1 : 0] : lb[t - 1][wdn][R - 1][lane];
+                st.yp[0][0] = i < R - 1 ? cc[i < R - 1 ? i + 1 : 0] : lb[t - 1][wup][0][lane];
+                st.ix = x;
+                st.iy = yg[i];
+                st.iz = zp;
                 T av[1] = {fq[t][i]}, bv[1] = {T(0)};
                 T o[1];
                 double rv[1];
-                Op::apply(st, av, bv, a.p, o, rv, a.operand);
+                Op::apply(st, av, bv, pt, o, rv, a.operand);
                 const bool inside = z_in && y_in[i] && x_in;
                 const T val = (dir && !inside) ? bcv : o[0];
                 if (t == k) {
@@ -175,7 +220,6 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
                 below[i] = val;
             }
         }
-        __syncthreads();
     }
     if (RED) block_reduce(acc, a.ra, tile);
 }

@@ -120,3 +120,110 @@ def test_sor_needs_far_fewer_sweeps_than_jacobi(ctx):
         assert math.sqrt(oracle.sumsq(r) / oracle.sumsq(f)) <= 1e-8 * 1.0001
         res[name] = st["sweeps"]
     assert res["sor"] * 10 < res["jacobi"], res
+
+
+def _inplace_passes(ctx, u, f, dt, omega, h2, c0, k, reduce=None):
+    gu = ctx.grid(u.shape, dt, halo=1, data=u)
+    gf = ctx.grid(u.shape, dt, halo=0, data=f)
+    r = None
+    for q in range(k):
+        last = q == k - 1
+        r = ctx.do_all(G.K_RBGS, [gu, gf], [gu], p=(omega, h2, (c0 + q) % 2),
+                       reduce=reduce if last else None)
+    return gu.numpy(), r
+
+
+@pytest.mark.parametrize("shape", [(9, 37, 203), (2, 3, 5), (1, 1, 1), (21, 50, 120)])
+@pytest.mark.parametrize("dt", [G.F64, G.F32])
+def test_rbgs_blocked_equals_inplace_passes(ctx, shape, dt):
+    """k colour passes in one blocked pass (Sections 2 and 3) against k
+    in-place colour passes: bit for bit, for every k and first colour; the
+    fused update norm of the last pass agrees to reduction-order rounding."""
+    g = np.random.default_rng(33)
+    u = g.standard_normal(shape)
+    f = g.standard_normal(shape)
+    if dt == G.F32:
+        u, f = u.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64)
+    omega, h2 = 1.7, 0.3
+    gu = ctx.grid(shape, dt, halo=1, data=u)
+    gf = ctx.grid(shape, dt, halo=0, data=f)
+    go = ctx.grid(shape, dt, halo=1)
+    for k in (1, 2, 3, 4):
+        for c0 in (0, 1):
+            ref, l2_ref = _inplace_passes(ctx, u, f, dt, omega, h2, c0, k, reduce=(G.R_L2, G.RV_UPDATE))
+            l2 = ctx.do_all(G.K_RBGS_TB, [gu, gf], [go], p=(omega, h2, c0, k), reduce=(G.R_L2, G.RV_UPDATE))
+            assert np.array_equal(go.numpy(), ref), (k, c0)
+            assert abs(l2 - l2_ref) <= 1e-12 * max(l2_ref, 1e-300) * (1 if dt == G.F64 else 1e3), (k, c0)
+
+
+def test_rbgs_blocked_matches_oracle(ctx):
+    shape = (12, 29, 75)
+    g = np.random.default_rng(34)
+    u = g.standard_normal(shape)
+    f = g.standard_normal(shape)
+    omega, h2 = 1.45, 0.2
+    gu = ctx.grid(shape, G.F64, halo=1, data=u)
+    gf = ctx.grid(shape, G.F64, halo=0, data=f)
+    go = ctx.grid(shape, G.F64, halo=1)
+    ctx.do_all(G.K_RBGS_TB, [gu, gf], [go], p=(omega, h2, 1, 4))
+    cur = u
+    for q in range(4):
+        cur, _, _ = oracle.rbgs_pass(cur, f, omega, h2, (1 + q) % 2, 0.0)
+    scale = 8 * np.abs(u).max() + h2 * np.abs(f).max()
+    assert np.abs(go.numpy() - cur).max() <= 4e-14 * scale
+
+
+def test_rbgs_blocked_errors(ctx):
+    shape = (6, 7, 40)
+    gu = ctx.grid(shape, G.F64, halo=1).fill(1.0)
+    go = ctx.grid(shape, G.F64, halo=1)
+
+    def err(fn):
+        with pytest.raises(G.GsclError) as e:
+            fn()
+        return e.value.code
+
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu], [go], p=(1.0, 1.0, 2, 2))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu], [go], p=(1.0, 1.0, 0, 5))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu], [go], p=(1.0, 1.0, 0, 1.5))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu], [go], p=(1.0, 0.0, 0, 2))) == G.ERR_ARG
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu], [gu], p=(1.0, 1.0, 0, 2))) == G.ERR_ALIAS
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gu, go], [go], p=(1.0, 1.0, 0, 2))) == G.ERR_ALIAS
+    gp = ctx.grid(shape, G.F64, halo=1, bc=G.PERIODIC).fill(1.0)
+    gq = ctx.grid(shape, G.F64, halo=1, bc=G.PERIODIC)
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [gp], [gq], p=(1.0, 1.0, 0, 2))) == G.ERR_UNSUPPORTED
+    g8 = ctx.grid(shape, G.U8, halo=1)
+    h8 = ctx.grid(shape, G.U8, halo=1)
+    assert err(lambda: ctx.do_all(G.K_RBGS_TB, [g8], [h8], p=(1.0, 1.0, 0, 2))) == G.ERR_DTYPE
+
+
+@pytest.mark.parametrize("n,S", [(150, 6), (146, 4)])
+def test_blocked_sor_solve_equals_inplace_solve(sctx, n, S):
+    """Grids of 144^3 points or more run the SOR chunks as blocked passes
+    (2S colour passes: S = 6 -> 4+4+2+2, S = 4 -> 4+4): the same stopping
+    sweep and the same iterate, bit for bit, as in-place colour passes with
+    the same residual checks, and the oracle accepts the answer."""
+    ctx = sctx
+    req = W.poisson_requests(count=1, qps=float("inf"), nmin=n, nmax=n, seed_index=n)[0]
+    _, f = W.poisson_fields(req)
+    gf = ctx.grid(f.shape, G.F64, halo=0, data=f)
+    u = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    st = ctx.solve(G.K_RBGS, [u], [gf], omega=0.0, h2=req.h2, rtol=1e-8, check_every=S)
+    w = _opt_omega(n)
+    v = ctx.grid(f.shape, G.F64, halo=1).fill(0.0)
+    r = ctx.grid(f.shape, G.F32, halo=0)
+    fn2 = oracle.sumsq(f)
+    sweeps = 0
+    while True:
+        for q in range(2 * S):
+            ctx.do_all(G.K_RBGS, [v, gf], [v], p=(w, req.h2, q % 2))
+        sweeps += S
+        res2 = ctx.do_all(G.K_POISSON_RESID, [v, gf], [r], p=(0.0, req.h2), reduce=(G.R_SUMSQ, G.RV_RESIDUAL))
+        if math.sqrt(res2 / fn2) <= 1e-8:
+            break
+        assert sweeps < 20000
+    assert st["sweeps"] == sweeps
+    got = u.numpy()
+    assert np.array_equal(got, v.numpy())
+    _, _, res = oracle.wjacobi_sweep(got, f, 1.0, req.h2)
+    assert math.sqrt(oracle.sumsq(res) / fn2) <= 1e-8 * 1.0001
