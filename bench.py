@@ -636,6 +636,27 @@ class Serve:
                                        realtime=False, kind=self.G.K_RBGS).summary()
         return bat, seq
 
+    def cpu_baseline(self, budget_s=20.0):
+        """The oracle's checked weighted-Jacobi solve (FP64, same omega, rtol
+        and check period as the sequential GPU path) on the sample's requests
+        in increasing size, until about budget_s of CPU work: solves/s on
+        that subsample of the smallest requests, an upper bound on the
+        oracle's rate over the whole sample."""
+        import oracle
+        done, sizes = 0, []
+        t0 = time.perf_counter()
+        for r in sorted(self.reqs, key=lambda r: r.n):
+            _, _, _, conv = oracle.poisson_solve(self.fields[r.rid], r.h2, 6 / 7, self.rtol, 64, 10 ** 7)
+            assert conv
+            done += 1
+            sizes.append(r.n)
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": round(done / dt, 4), "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"the {done} smallest of the {self.count} requests (N = {min(sizes)}..{max(sizes)}) "
+                          f"solved to {self.rtol} in {dt:.1f} s"}
+
     def config(self):
         return {"workload": f"{self.count} Poisson solve requests (one seeded sample), cube sides log-uniform "
                             f"in [{self.nmin},{self.nmax}], 3 sine modes, weighted Jacobi omega=6/7 to "
@@ -817,6 +838,8 @@ def serve_main(args, ctx, wl):
            "speedup_vs_sequential_f64": round(bat["solves_per_s"] / seq["solves_per_s"], 3),
            "batched_rbsor_f64_closed_loop": sor_bat, "sequential_rbsor_f64_closed_loop": sor_seq,
            "roofline": None, "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = wl.cpu_baseline()
     ctx.end()
     ctx.finalize()
     print(json.dumps(out), flush=True)
