@@ -571,8 +571,9 @@ class Image:
 
 class Serve:
     """Stream of Poisson solve requests: batched mixed-precision serving
-    (continuous batching, F32 correction sweeps, F64 residual) against the
-    one-solve-at-a-time F64 solver, both to the same relative residual.
+    (continuous batching, F32 correction sweeps as temporally blocked passes of
+    4, F64 residual) against the one-solve-at-a-time F64 solver, both to the
+    same relative residual.
 
     Capacity is measured closed-loop (every request queued at t = 0); latency
     is measured with Poisson arrivals offered at a fraction of the measured
@@ -662,7 +663,8 @@ class Serve:
                             f"in [{self.nmin},{self.nmax}], 3 sine modes, weighted Jacobi omega=6/7 to "
                             f"relative residual {self.rtol}; value = closed-loop capacity, latency at "
                             f"Poisson arrivals offered at {self.load} x that capacity",
-                "serving": "continuous batching, F32 correction sweeps + F64 residual (refinement)"}
+                "serving": "continuous batching, F32 correction sweeps (temporally blocked passes of 4) + "
+                           "F64 residual (refinement)"}
 
 
 class Reduce:

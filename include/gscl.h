@@ -391,7 +391,10 @@ typedef struct {
     size_t hbm_budget;
     int64_t max_sweeps;         /* per request; reaching it retires as not converged */
     int32_t method;             /* GSCL_BATCH_JACOBI (weighted Jacobi) or GSCL_BATCH_RBGS */
-    int32_t reserved;
+    int32_t sweeps_per_pass;    /* Jacobi: 0 or 1 = one sweep per pass; k in 2..4 = temporally
+                                   blocked passes of k sweeps (GSCL_K_WJACOBI_TB tiles, the
+                                   same sweeps bit for bit); sweeps_per_step must then be a
+                                   multiple of 2k */
 } gscl_batch_desc;
 typedef struct {
     int32_t state;              /* 0 free, 1 running, 2 converged, 3 failed */

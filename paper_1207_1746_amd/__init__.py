@@ -72,7 +72,7 @@ class SolveStats(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("max_slots", _i32), ("precision", _i32), ("sweeps_per_step", _i32),
                 ("use_graph", _i32), ("omega", _f64), ("rtol", _f64), ("hbm_budget", ctypes.c_size_t),
-                ("max_sweeps", _i64), ("method", _i32), ("reserved", _i32)]
+                ("max_sweeps", _i64), ("method", _i32), ("sweeps_per_pass", _i32)]
 
 
 class SlotStats(ctypes.Structure):
@@ -437,16 +437,17 @@ class Graph:
 
 class Batch:
     """Batched multi-grid Poisson executor (gscl_batch_*).  method BATCH_JACOBI
-    sweeps weighted Jacobi (F64 or F32 refinement); BATCH_RBGS sweeps red-black
-    SOR in F64 (omega = 0: each slot's optimal model-problem weight)."""
+    sweeps weighted Jacobi (F64 or F32 refinement), optionally as temporally
+    blocked passes of sweeps_per_pass sweeps; BATCH_RBGS sweeps red-black SOR
+    in F64 (omega = 0: each slot's optimal model-problem weight)."""
 
     def __init__(self, ctx: Context, max_slots: int = 64, precision: int = PREC_F64,
                  sweeps_per_step: int = 32, use_graph: bool = True, omega: float = 6 / 7,
                  rtol: float = 1e-8, hbm_budget: int = 8 << 30, max_sweeps: int = 10 ** 7,
-                 method: int = BATCH_JACOBI):
+                 method: int = BATCH_JACOBI, sweeps_per_pass: int = 1):
         self.ctx = ctx
         bd = BatchDesc(max_slots, precision, sweeps_per_step, int(use_graph), omega, rtol, hbm_budget,
-                       max_sweeps, method, 0)
+                       max_sweeps, method, sweeps_per_pass)
         h = _vp()
         check(lib().gscl_batch_create(ctx.handle, ctypes.byref(bd), ctypes.byref(h)), "gscl_batch_create")
         self.handle = h

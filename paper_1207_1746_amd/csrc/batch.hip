@@ -24,6 +24,10 @@
 //   colour passes (the red points, then the black ones, each reading only
 //   the other colour), then an F64 residual pass of the current u with its
 //   norm and the stopping rule.
+// * Jacobi sweeps may run as temporally blocked passes of k sweeps (the
+//   wide-ghost-zone tiles of the blocked driver, bitwise the same sweeps):
+//   each slot then also has a blocked tile range, walked by a persistent
+//   kernel of 16-wave blocks.
 #include <math.h>
 #include <string.h>
 
@@ -33,6 +37,7 @@
 
 #include "api_internal.h"
 #include "ops.h"
+#include "tb7.h"
 
 namespace {
 
@@ -52,6 +57,8 @@ struct BSlot {
     float* rh;
     int ntx, nty, ncz, cz;
     int tile_begin, ntiles;
+    int tntx, tnty, tncz, tcz;   // blocked-pass tiles (sweeps_per_pass > 1)
+    int tb_begin, tb_ntiles;
 };
 
 struct BState {
@@ -65,15 +72,18 @@ struct BState {
 struct BHeader {
     int nslots;
     int total_tiles;
+    int total_tb_tiles;
 };
 
 enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2, MODE_RBGS = 3 };
 
+// slot owning global tile t (TB: of the blocked-pass tile list)
+template <bool TB = false>
 __device__ __forceinline__ int find_slot(const BSlot* __restrict__ s, int n, int t) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s[mid].tile_begin <= t) lo = mid;
+        if ((TB ? s[mid].tb_begin : s[mid].tile_begin) <= t) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -141,6 +151,57 @@ __global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict_
     }
 }
 
+// k Jacobi sweeps per pass over the blocked tiles of every running slot:
+// F64 u -> u2 (parity 0) or back, or F32 corrections d -> d2 or back with the
+// F32 residual as right-hand side.  RED: the residual of the last sweep's
+// input, per blocked tile, into the partials.
+template <int MODE, bool RED>
+__global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restrict__ slots, const BState* st,
+                                                           const BHeader* hdr, double* partials, int parity,
+                                                           double omega, int k) {
+    using T = typename std::conditional<MODE == MODE_F32, float, double>::type;
+    const int n = hdr->nslots, total = hdr->total_tb_tiles;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int si = find_slot<true>(slots, n, t);
+        const BSlot& s = slots[si];
+        if (st[s.id].state != 1) continue;
+        gk::TBArgs a;
+        a.g.nx = s.nx;
+        a.g.ny = s.ny;
+        a.g.nz = s.nz;
+        a.g.py = s.py;
+        a.g.pz = s.pz;
+        a.g.bc = gk::BC_DIRICHLET;
+        a.g.bcv = 0.0;
+        a.p[0] = omega;
+        a.p[1] = s.h2;
+        a.p[2] = s.ih2;
+        a.p[3] = 0.0;
+        a.k = k;
+        a.ntx = s.tntx;
+        a.nty = s.tnty;
+        a.ncz = s.tncz;
+        a.cz = s.tcz;
+        a.operand = gk::RV_RESIDUAL;
+        a.ra.partials = partials;
+        a.ra.result = nullptr;
+        a.ra.op = gk::R_SUMSQ;
+        a.ra.eps = 0.0;
+        if (MODE == MODE_F32) {
+            a.u = parity ? (const void*)s.d2 : (const void*)s.d;
+            a.out = parity ? (void*)s.d : (void*)s.d2;
+            a.f = s.rh;
+        } else {
+            a.u = parity ? (const void*)s.u2 : (const void*)s.u;
+            a.out = parity ? (void*)s.u : (void*)s.u2;
+            a.f = s.f;
+        }
+        double acc = 0.0;
+        gk::tb7_tile<T, true, gk::TB_KMAX, RED, false>(a, t - s.tb_begin, acc);
+        if (RED) gk::block_reduce(acc, a.ra, t);
+    }
+}
+
 // u += d and d = 0 over every tile of running slots (refinement update).
 __global__ __launch_bounds__(64 * BNW) void batch_update(const BSlot* __restrict__ slots, const BState* st,
                                                          const BHeader* hdr) {
@@ -164,16 +225,18 @@ __global__ __launch_bounds__(64 * BNW) void batch_update(const BSlot* __restrict
 }
 
 // Per-slot fold of the residual partials and the stopping rule.
+// tb: the partials come from the blocked-pass tiles.
 __global__ __launch_bounds__(256) void batch_finish(const BSlot* __restrict__ slots, BState* st,
                                                     const BHeader* hdr, const double* partials, double rtol2,
-                                                    int sweeps_per_check, long long max_sweeps, int ir) {
+                                                    int sweeps_per_check, long long max_sweeps, int ir, int tb) {
     const int i = blockIdx.x;
     if (i >= hdr->nslots) return;
     const BSlot& s = slots[i];
     BState& b = st[s.id];
     if (b.state != 1) return;
+    const int begin = tb ? s.tb_begin : s.tile_begin, count = tb ? s.tb_ntiles : s.ntiles;
     double a = 0.0;
-    for (int k = threadIdx.x; k < s.ntiles; k += blockDim.x) a += partials[s.tile_begin + k];
+    for (int k = threadIdx.x; k < count; k += blockDim.x) a += partials[begin + k];
     __shared__ double wp[4];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
@@ -316,6 +379,12 @@ extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_ba
         return gscl_fail(GSCL_ERR_ARG, "red-black batches need 0 <= omega < 2");
     if (bd->sweeps_per_step < 2 || bd->sweeps_per_step % 2)
         return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be even and >= 2");
+    if (bd->sweeps_per_pass < 0 || bd->sweeps_per_pass > gk::TB_KMAX)
+        return gscl_fail(GSCL_ERR_ARG, "sweeps_per_pass must be 0..%d", gk::TB_KMAX);
+    if (bd->sweeps_per_pass > 1 && bd->method != GSCL_BATCH_JACOBI)
+        return gscl_fail(GSCL_ERR_UNSUPPORTED, "blocked passes are for Jacobi batches");
+    if (bd->sweeps_per_pass > 1 && bd->sweeps_per_step % (2 * bd->sweeps_per_pass))
+        return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be a multiple of 2 * sweeps_per_pass");
     if (!(bd->rtol > 0) || bd->max_sweeps < 1 || bd->hbm_budget < 4096)
         return gscl_fail(GSCL_ERR_ARG, "rtol, max_sweeps and hbm_budget must be positive");
     gscl_batch* b = new gscl_batch();
@@ -386,19 +455,22 @@ static bool batch_ok(const gscl_batch* b) { return b && b->magic == BATCH_MAGIC;
 static int upload_table(gscl_batch* b) {
     gscl_ctx* c = b->ctx;
     GSCL_HIP(hipEventSynchronize(b->upload_done));  // staging buffers free again
-    int n = 0, tiles = 0;
+    int n = 0, tiles = 0, tb_tiles = 0;
     for (int id = 0; id < b->desc.max_slots; ++id) {
         if (!b->used[id]) continue;
         BSlot s = b->slot[id];
         s.tile_begin = tiles;
         tiles += s.ntiles;
+        s.tb_begin = tb_tiles;
+        tb_tiles += s.tb_ntiles;
         b->h_slots[n++] = s;
     }
-    if (tiles > b->partial_cap) {
+    const int need = std::max(tiles, tb_tiles);
+    if (need > b->partial_cap) {
         // grow the partials (invalidates a captured step graph)
         GSCL_HIP(hipStreamSynchronize(c->stream));
         GSCL_HIP(hipFree(b->d_partials));
-        b->partial_cap = std::max<int64_t>(tiles, 2 * b->partial_cap);
+        b->partial_cap = std::max<int64_t>(need, 2 * b->partial_cap);
         GSCL_HIP(hipMalloc(&b->d_partials, sizeof(double) * b->partial_cap));
         if (b->graph) {
             gscl_graph_destroy(b->graph);
@@ -407,6 +479,7 @@ static int upload_table(gscl_batch* b) {
     }
     b->h_hdr->nslots = n;
     b->h_hdr->total_tiles = tiles;
+    b->h_hdr->total_tb_tiles = tb_tiles;
     if (n) GSCL_HIP(hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(BSlot) * n, hipMemcpyHostToDevice, c->stream));
     GSCL_HIP(hipMemcpyAsync(b->d_hdr, b->h_hdr, sizeof(BHeader), hipMemcpyHostToDevice, c->stream));
     GSCL_HIP(hipEventRecord(b->upload_done, c->stream));
@@ -477,6 +550,23 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     s.nty = (s.ny + BNW - 1) / BNW;
     s.ncz = (s.nz + s.cz - 1) / s.cz;
     s.ntiles = s.ntx * s.nty * s.ncz;
+    const int kp = b->desc.sweeps_per_pass;
+    if (kp > 1) {
+        // blocked tiles: (64 - 2k) x (32 - 2k) outputs; z chunk a power of
+        // two up to tiles per plane * nz / 160 (the standalone rule), but at
+        // least 16 planes: the slots of a batch fill the chip together, and
+        // short chunks pay the 2k warm-up planes of every tile (measured on
+        // mixed batches of 32^3..96^3 grids: 16 is best, 2x over 1-4)
+        const int ox = 64 - 2 * kp, oy = gk::TB_ROWS - 2 * kp;
+        s.tntx = (s.nx + ox - 1) / ox;
+        s.tnty = (s.ny + oy - 1) / oy;
+        const int64_t want = std::max<int64_t>(1, (int64_t)s.tntx * s.tnty * s.nz / 160);
+        int cz = 16;
+        while (cz * 2 <= want && cz < 64) cz *= 2;
+        s.tcz = std::min(cz, s.nz);
+        s.tncz = (s.nz + s.tcz - 1) / s.tcz;
+        s.tb_ntiles = s.tntx * s.tnty * s.tncz;
+    }
     b->slot[id] = s;
     b->used[id] = true;
     b->work_ptr[id] = mem;
@@ -507,6 +597,9 @@ static int enqueue_step(gscl_batch* b) {
     const double rtol2 = b->desc.rtol * b->desc.rtol;
     const dim3 grid(b->persist_blocks), blk(64 * BNW);
     const int ms = b->desc.max_slots;
+    const int kp = b->desc.sweeps_per_pass;
+    // blocked passes: one 16-wave block per CU in FP64, two in FP32
+    const dim3 tgrid(b->desc.precision == GSCL_PREC_F64 ? 256 : 512), tblk(64 * gk::TB_NW);
     if (b->desc.method == GSCL_BATCH_RBGS) {
         for (int k = 0; k < 2 * S; ++k)
             hipLaunchKernelGGL((batch_sweep<MODE_RBGS, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
@@ -514,7 +607,19 @@ static int enqueue_step(gscl_batch* b) {
         hipLaunchKernelGGL((batch_sweep<MODE_RESID, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
                            b->d_partials, 0, 0.0);
         hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
-                           rtol2, S, (long long)b->desc.max_sweeps, 0);
+                           rtol2, S, (long long)b->desc.max_sweeps, 0, 0);
+    } else if (b->desc.precision == GSCL_PREC_F64 && kp > 1) {
+        const int np = S / kp;  // even: the step ends in u
+        for (int q = 0; q < np; ++q) {
+            if (q + 1 < np)
+                hipLaunchKernelGGL((batch_tb<MODE_F64, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, q & 1, b->desc.omega, kp);
+            else
+                hipLaunchKernelGGL((batch_tb<MODE_F64, true>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, q & 1, b->desc.omega, kp);
+        }
+        hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
+                           rtol2, S, (long long)b->desc.max_sweeps, 0, 1);
     } else if (b->desc.precision == GSCL_PREC_F64) {
         for (int k = 1; k <= S; ++k) {
             const int parity = (k - 1) & 1;
@@ -526,15 +631,21 @@ static int enqueue_step(gscl_batch* b) {
                                    b->d_partials, parity, b->desc.omega);
         }
         hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
-                           rtol2, S, (long long)b->desc.max_sweeps, 0);
+                           rtol2, S, (long long)b->desc.max_sweeps, 0, 0);
     } else {
         hipLaunchKernelGGL((batch_sweep<MODE_RESID, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
                            b->d_partials, 0, b->desc.omega);
         hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
-                           rtol2, S, (long long)b->desc.max_sweeps, 1);
-        for (int k = 1; k <= S; ++k)
-            hipLaunchKernelGGL((batch_sweep<MODE_F32, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
-                               b->d_partials, (k - 1) & 1, b->desc.omega);
+                           rtol2, S, (long long)b->desc.max_sweeps, 1, 0);
+        if (kp > 1) {
+            for (int q = 0; q < S / kp; ++q)
+                hipLaunchKernelGGL((batch_tb<MODE_F32, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, q & 1, b->desc.omega, kp);
+        } else {
+            for (int k = 1; k <= S; ++k)
+                hipLaunchKernelGGL((batch_sweep<MODE_F32, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                                   b->d_partials, (k - 1) & 1, b->desc.omega);
+        }
         hipLaunchKernelGGL(batch_update, grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr);
     }
     GSCL_HIP(hipGetLastError());

@@ -67,8 +67,11 @@ __device__ __forceinline__ double lane_shift(double v) {
 }
 constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
 
+// One output tile (index `tile` of a.ntx x a.nty x a.ncz): k levels over its
+// z chunk; with RED, the fused operand of level k is added to acc.  Every
+// thread of the 16-wave block calls it.
 template <class T, bool HAS_F, int KMAX, bool RED, bool RB>
-__global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
+__device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double& acc) {
     using Op = typename std::conditional<RB, OpRBGS<T, HAS_F>, OpWJacobi<T, T, 3, HAS_F>>::type;
     constexpr int R = TB_RPW;
     // the rows every wave stages per level, in two copies alternating by
@@ -79,8 +82,6 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
     const Geo& g = a.g;
     const int k = a.k;
     const int ox = 64 - 2 * k, oy = TB_ROWS - 2 * k;  // output tile
-    const int ntiles = a.ntx * a.nty * a.ncz;
-    const int tile = xcd_remap(blockIdx.x, ntiles);
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // waves whose rows border this wave's (the block's edge waves read their
     // own rows there: those rows lie in the ghost zone, never written)
@@ -146,7 +147,6 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
         nf[i] = load_f(s_begin - 1, i);
     }
 
-    double acc = 0.0;
     for (int s = s_begin; s < s_end; ++s) {
         T cur[R];
 #pragma unroll
@@ -221,6 +221,13 @@ __global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
             }
         }
     }
+}
+
+template <class T, bool HAS_F, int KMAX, bool RED, bool RB>
+__global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
+    const int tile = xcd_remap(blockIdx.x, a.ntx * a.nty * a.ncz);
+    double acc = 0.0;
+    tb7_tile<T, HAS_F, KMAX, RED, RB>(a, tile, acc);
     if (RED) block_reduce(acc, a.ra, tile);
 }
 

@@ -69,12 +69,17 @@ class SolveServer:
     def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
                  rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
                  hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7,
-                 pipelined: bool = True, method: int = G.BATCH_JACOBI):
+                 pipelined: bool = True, method: int = G.BATCH_JACOBI, sweeps_per_pass: int = 4):
         self.ctx = ctx
         self.pipelined = pipelined
+        # Jacobi sweeps run as temporally blocked passes of 4 (the same sweeps
+        # bit for bit) when the step length allows it
+        if method != G.BATCH_JACOBI or sweeps_per_step % (2 * sweeps_per_pass):
+            sweeps_per_pass = 1
         self.batch = G.Batch(ctx, max_slots=max_slots, precision=precision,
                              sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,
-                             rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps, method=method)
+                             rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps, method=method,
+                             sweeps_per_pass=sweeps_per_pass)
 
     def _admit(self, job: Job, now: float) -> bool:
         shape = (job.n, job.n, job.n)

@@ -69,6 +69,40 @@ def test_thomas_matches_oracle(ctx, axis, direction):
     assert np.array_equal(x.numpy(), ex)
 
 
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("dt", [G.F64, G.F32])
+def test_lines_along_x_several_blocks(ctx, direction, dt):
+    """Lines along x run 256 to a block in chunks of 8 or 16 cells: 350 lines
+    (one full block and a partial one) of 203 cells (a ragged last chunk in
+    either order), recurrence and both Thomas passes against the oracle."""
+    shape = (5, 70, 203)
+    g = np.random.default_rng(46)
+    a = g.uniform(-0.95, 0.95, shape)
+    b = g.standard_normal(shape)
+    lo, up = g.uniform(-1, 1, shape), g.uniform(-1, 1, shape)
+    di = 2.5 + g.uniform(0, 1, shape)
+    if dt == G.F32:
+        a, b, lo, up, di = (v.astype(np.float32).astype(np.float64) for v in (a, b, lo, up, di))
+    go = ctx.grid(shape, dt, halo=0)
+    ctx.do_line(G.K_LINE_RECUR, 0, direction, [_grid(ctx, a, dt), _grid(ctx, b, dt)], [go], p=(0.25,))
+    ex = oracle.line_recur(a, b, 0, direction, seed=0.25)
+    gs = [_grid(ctx, v, dt) for v in (lo, di, up, b)]
+    cp, dp, x = (ctx.grid(shape, dt, halo=0) for _ in range(3))
+    ctx.do_line(G.K_TRIDIAG_FWD, 0, direction, gs, [cp, dp])
+    ctx.do_line(G.K_TRIDIAG_BACK, 0, -direction, [cp, dp], [x])
+    ecp, edp = oracle.tridiag_fwd(lo, di, up, b, 0, direction)
+    exx = oracle.tridiag_back(ecp, edp, 0, -direction)
+    if dt == G.F64:
+        assert np.array_equal(go.numpy(), ex)
+        assert np.array_equal(cp.numpy(), ecp) and np.array_equal(dp.numpy(), edp)
+        assert np.array_equal(x.numpy(), exx)
+    else:
+        tol = 64 * 2.0 ** -24
+        assert np.abs(go.numpy() - ex).max() <= tol * (np.abs(ex).max() + 1)
+        # diagonally dominant systems: the F32 solve stays within a few roundings
+        assert np.abs(x.numpy() - exx).max() <= 16 * tol * (np.abs(exx).max() + 1)
+
+
 def test_vertical_tridiagonal_solves_residual(ctx):
     """256 x 256 columns of 128 levels (climate-style implicit vertical
     solves), F64: every column's residual |A x - rhs| is at rounding level."""

@@ -115,10 +115,10 @@ def test_vc13_solve_per_precision(ctx, prec, dt):
 
 
 def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8, method=G.BATCH_JACOBI,
-                 omega=6 / 7):
+                 omega=6 / 7, sweeps_per_pass=1):
     """Run requests through one batch; admit_at[i] = step index to admit request i."""
     b = G.Batch(ctx, max_slots=8, precision=prec, sweeps_per_step=S, use_graph=use_graph, rtol=rtol,
-                hbm_budget=1 << 30, method=method, omega=omega)
+                hbm_budget=1 << 30, method=method, omega=omega, sweeps_per_pass=sweeps_per_pass)
     admit_at = admit_at or [0] * len(reqs)
     grids = {}
     out = {}
@@ -218,6 +218,34 @@ def test_batch_rbgs_errors_and_footprint(ctx):
     assert rb.footprint((40, 40, 40)) < jb.footprint((40, 40, 40))
     jb.close()
     rb.close()
+
+
+@pytest.mark.parametrize("prec,k", [(G.PREC_F64, 4), (G.PREC_F64, 2), (G.PREC_F32_IR, 4)])
+def test_batch_blocked_passes_equal_plain_sweeps(ctx, prec, k):
+    """Jacobi slots swept as temporally blocked passes of k sweeps: the same
+    iterates bit for bit as one-sweep passes (same stopping step), and alone
+    equals among others."""
+    reqs = [_req(n, seed=n + 3, rid=i) for i, n in enumerate((17, 37, 45, 24))]
+    S = 16
+    plain = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3])
+    blocked = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3], sweeps_per_pass=k)
+    for i, r in enumerate(reqs):
+        assert blocked[i][1]["state"] == 2
+        assert blocked[i][1]["sweeps"] == plain[i][1]["sweeps"], i
+        assert np.array_equal(blocked[i][0], plain[i][0]), i
+        alone = _batch_solve(ctx, [r], prec, S, sweeps_per_pass=k, use_graph=False)[0]
+        assert np.array_equal(alone[0], blocked[i][0]) and alone[1]["sweeps"] == blocked[i][1]["sweeps"], i
+        _, f = W.poisson_fields(r)
+        assert _oracle_rel_residual(blocked[i][0], f, r.h2) <= 1e-8 * 1.01
+
+
+def test_batch_blocked_pass_errors(ctx):
+    for kw, code in (({"sweeps_per_pass": 5}, G.ERR_ARG), ({"sweeps_per_pass": -1}, G.ERR_ARG),
+                     ({"sweeps_per_pass": 4, "sweeps_per_step": 12}, G.ERR_ARG),
+                     ({"sweeps_per_pass": 2, "method": G.BATCH_RBGS}, G.ERR_UNSUPPORTED)):
+        with pytest.raises(G.GsclError) as e:
+            G.Batch(ctx, **{"sweeps_per_step": 16, **kw})
+        assert e.value.code == code, kw
 
 
 def test_batch_budget_admission(ctx):
