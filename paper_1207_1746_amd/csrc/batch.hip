@@ -452,9 +452,42 @@ static bool batch_ok(const gscl_batch* b) { return b && b->magic == BATCH_MAGIC;
 
 // Rebuild the compact table (admitted slots in id order, tile prefix sums) and
 // upload it on the context stream.
+// Blocked tiles of a slot: (64 - 2k) x (32 - 2k) outputs; z chunk a power of
+// two up to tiles per plane * nz / 160 (the standalone rule), but at least
+// czmin planes: the slots of a batch fill the chip together, and short chunks
+// pay the 2k warm-up planes of every tile (measured on mixed batches of
+// 32^3..96^3 grids: czmin 16 is best, 2x over 1-4).
+constexpr int TB_CZMIN = 16;
+static void set_tb_tiles(BSlot& s, int kp, int czmin) {
+    const int ox = 64 - 2 * kp, oy = gk::TB_ROWS - 2 * kp;
+    s.tntx = (s.nx + ox - 1) / ox;
+    s.tnty = (s.ny + oy - 1) / oy;
+    const int64_t want = std::max<int64_t>(1, (int64_t)s.tntx * s.tnty * s.nz / 160);
+    int cz = czmin;
+    while (cz * 2 <= want && cz < 64) cz *= 2;
+    s.tcz = std::min(cz, s.nz);
+    s.tncz = (s.nz + s.tcz - 1) / s.tcz;
+    s.tb_ntiles = s.tntx * s.tnty * s.tncz;
+}
+
 static int upload_table(gscl_batch* b) {
     gscl_ctx* c = b->ctx;
     GSCL_HIP(hipEventSynchronize(b->upload_done));  // staging buffers free again
+    if (b->desc.sweeps_per_pass > 1 && b->desc.precision != GSCL_PREC_F64) {
+        // Refinement batches: the blocked passes carry no reduction, so their
+        // tiling changes no result; when few slots are left (the tail of a
+        // stream), shorter chunks spread the remaining work over more CUs:
+        // halve the minimum chunk until the batch has 512 blocked tiles.
+        for (int czmin = TB_CZMIN;; czmin /= 2) {
+            int64_t total = 0;
+            for (int id = 0; id < b->desc.max_slots; ++id)
+                if (b->used[id]) {
+                    set_tb_tiles(b->slot[id], b->desc.sweeps_per_pass, czmin);
+                    total += b->slot[id].tb_ntiles;
+                }
+            if (total >= 512 || czmin == 1) break;
+        }
+    }
     int n = 0, tiles = 0, tb_tiles = 0;
     for (int id = 0; id < b->desc.max_slots; ++id) {
         if (!b->used[id]) continue;
@@ -550,23 +583,7 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     s.nty = (s.ny + BNW - 1) / BNW;
     s.ncz = (s.nz + s.cz - 1) / s.cz;
     s.ntiles = s.ntx * s.nty * s.ncz;
-    const int kp = b->desc.sweeps_per_pass;
-    if (kp > 1) {
-        // blocked tiles: (64 - 2k) x (32 - 2k) outputs; z chunk a power of
-        // two up to tiles per plane * nz / 160 (the standalone rule), but at
-        // least 16 planes: the slots of a batch fill the chip together, and
-        // short chunks pay the 2k warm-up planes of every tile (measured on
-        // mixed batches of 32^3..96^3 grids: 16 is best, 2x over 1-4)
-        const int ox = 64 - 2 * kp, oy = gk::TB_ROWS - 2 * kp;
-        s.tntx = (s.nx + ox - 1) / ox;
-        s.tnty = (s.ny + oy - 1) / oy;
-        const int64_t want = std::max<int64_t>(1, (int64_t)s.tntx * s.tnty * s.nz / 160);
-        int cz = 16;
-        while (cz * 2 <= want && cz < 64) cz *= 2;
-        s.tcz = std::min(cz, s.nz);
-        s.tncz = (s.nz + s.tcz - 1) / s.tcz;
-        s.tb_ntiles = s.tntx * s.tnty * s.tncz;
-    }
+    if (b->desc.sweeps_per_pass > 1) set_tb_tiles(s, b->desc.sweeps_per_pass, TB_CZMIN);
     b->slot[id] = s;
     b->used[id] = true;
     b->work_ptr[id] = mem;
