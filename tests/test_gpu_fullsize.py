@@ -136,3 +136,67 @@ def test_poisson_temporal_chunks_match_closed_form_trace(sctx, n, S):
     assert st["sweeps"] == expect
     _, _, res = oracle.wjacobi_sweep(u.numpy(), f, 6 / 7, req.h2)
     assert math.sqrt(oracle.sumsq(res) / oracle.sumsq(f)) <= 1e-8
+
+
+def test_rbgs_512_blocked_bitwise_and_sampled_oracle(ctx):
+    """The red-black benchmark workload at its size (512^3 FP64 with a
+    right-hand side, omega 1.9): four colour passes as one blocked pass equal
+    four in-place passes bit for bit, and sampled points of one in-place pass
+    match the oracle's pass on each point's 3^3 neighbourhood (zero outside
+    the domain, the Dirichlet value)."""
+    import torch
+    n = 512
+    shape = (n, n, n)
+    u0, h2 = W.jacobi_cube(n)
+    f = W.jacobi_rhs(n)
+    omega = 1.9
+    gu = ctx.grid(shape, G.F64, halo=1, data=u0)
+    gf = ctx.grid(shape, G.F64, halo=0, data=f)
+    a = ctx.grid(shape, G.F64, halo=1)
+    a.view.copy_(gu.view)
+    ctx.do_all(G.K_RBGS, [a, gf], [a], p=(omega, h2, 0))
+    # sampled points of the pass's colour (0): the oracle on the neighbourhood
+    g = np.random.default_rng(70)
+    pts = g.integers(0, n, size=(1200, 3))
+    pts = pts[(pts.sum(axis=1) % 2) == 0][:500]  # (k + j + i) even: the pass's colour
+    pts = np.vstack([pts, [[0, 0, 0], [n - 1, n - 1, 0], [n - 2, 0, n - 2]]])
+    got = a.view[torch.as_tensor(pts[:, 0]), torch.as_tensor(pts[:, 1]), torch.as_tensor(pts[:, 2])].cpu().numpy()
+    up = np.pad(u0, 1)
+    fp = np.pad(f, 1)
+    for (k, j, i), gv in zip(pts, got):
+        box = up[k:k + 3, j:j + 3, i:i + 3]
+        fbox = fp[k:k + 3, j:j + 3, i:i + 3]
+        ex = oracle.rbgs_pass(box, fbox, omega, h2, 1, 0.0)[0][1, 1, 1]  # centre (1,1,1) has odd parity
+        assert abs(gv - ex) <= 1e-14 * (8 * np.abs(box).max() + h2 * abs(fbox[1, 1, 1])), (k, j, i)
+    # the other colour is untouched
+    assert torch.equal(a.view[0, 0, 1], gu.view[0, 0, 1])
+    for c in (1, 0, 1):
+        ctx.do_all(G.K_RBGS, [a, gf], [a], p=(omega, h2, c))
+    go = ctx.grid(shape, G.F64, halo=1)
+    ctx.do_all(G.K_RBGS_TB, [gu, gf], [go], p=(omega, h2, 0, 4))
+    assert torch.equal(go.view, a.view)
+
+
+def test_tridiag_512_sampled_columns(ctx):
+    """The line benchmark workload at its size: tridiagonal solves along k for
+    every column of a 512^3 FP64 grid (elimination do_k_inc, substitution
+    do_k_dec); sampled columns equal the oracle's Thomas solve bit for bit."""
+    import torch
+    n = 512
+    shape = (n, n, n)
+    gen = torch.Generator(device="cuda").manual_seed(12071746)
+    grids = []
+    for lo, hi in ((-1.0, 1.0), (2.5, 3.5), (-1.0, 1.0), (-1.0, 1.0)):
+        gg = ctx.grid(shape, G.F64, halo=0)
+        gg.view.copy_(torch.rand(shape, dtype=torch.float64, device="cuda", generator=gen) * (hi - lo) + lo)
+        grids.append(gg)
+    cp, dp, x = (ctx.grid(shape, G.F64, halo=0) for _ in range(3))
+    ctx.do_line(G.K_TRIDIAG_FWD, 2, 1, grids, [cp, dp])
+    ctx.do_line(G.K_TRIDIAG_BACK, 2, -1, [cp, dp], [x])
+    g = np.random.default_rng(71)
+    cols = [(0, 0), (n - 1, n - 1), (0, n - 1)] + [tuple(c) for c in g.integers(0, n, size=(13, 2))]
+    for j, i in cols:
+        col = [gg.view[:, j, i].cpu().numpy().reshape(n, 1, 1) for gg in grids]
+        ecp, edp = oracle.tridiag_fwd(*col, 2, 1)
+        ex = oracle.tridiag_back(ecp, edp, 2, -1)
+        assert np.array_equal(x.view[:, j, i].cpu().numpy(), ex.reshape(n)), (j, i)
