@@ -105,3 +105,20 @@ def test_image_special_cases(ctx):
     b, l = gb.numpy()[0], gl.numpy()[0]
     assert np.all(b[7:12, 18:23] == 10) and b.sum() == 250
     assert l[9, 20] == -1020 and np.count_nonzero(l) == 5
+
+
+def test_reduce_512_full_size(ctx):
+    """The reduction benchmark's size (512^3 FP64): the index sum is exact
+    (n(n-1)/2 = 2^53 - 2^26, every partial sum an integer below 2^53), and
+    the L2 norm of uniform data agrees with the pairwise oracle to 1e-12."""
+    import torch
+    n = 512
+    shape = (n, n, n)
+    g = ctx.grid(shape, G.F64, halo=0)
+    g.view.copy_(torch.arange(n ** 3, dtype=torch.float64, device="cuda").reshape(shape))
+    assert ctx.do_reduce(G.R_SUM, g) == float(2 ** 53 - 2 ** 26)
+    assert ctx.do_reduce(G.R_MAXABS, g) == float(n ** 3 - 1)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    g.view.copy_(torch.rand(shape, dtype=torch.float64, device="cuda", generator=gen))
+    ref = math.sqrt(oracle.sumsq(g.view.cpu().numpy()))
+    assert abs(ctx.do_reduce(G.R_L2, g) - ref) <= 1e-12 * ref
