@@ -163,6 +163,7 @@ class VarCoef:
 class Jacobi:
     key = "wjacobi_f64"
     bytes_per_point = 16
+    event_stride = 3      # time every 3rd of the 9 plain sweeps (30 per 10-step run)
 
     def __init__(self, ctx, n=64, sweeps=10):
         import torch
@@ -945,7 +946,7 @@ def main():
             "traffic": traffic,
             "kernel_ms": round(kmean_ms, 5),
             "launches_timed": nk,
-            "launch_sampling": f"HIP events around every {ev.stride}th launch of the kernel",
+            "launch_sampling": f"HIP events around 1 of every {ev.stride} launches of the kernel",
             "alg_bytes_per_launch": per_launch_bytes,
         },
         "cpu_baseline": None,
