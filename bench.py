@@ -180,18 +180,22 @@ class Jacobi:
         self.points = n ** 3
         self.units_per_step = self.points * sweeps
         self.unit = "Gpts/s"
+        # the ten launches of a step, with their arguments built once
+        self.calls = []
+        for k in range(sweeps):
+            src, dst = (self.a, self.b) if k % 2 == 0 else (self.b, self.a)
+            last = k == sweeps - 1
+            self.calls.append(ctx.prepare_all(G.K_WJACOBI, [src], [dst], p=(1.0, self.h2),
+                                              reduce=(G.R_L2, G.RV_UPDATE) if last else None,
+                                              dev_result=self.res if last else None))
 
     def step(self, ev=None):
-        G = self.G
-        for k in range(self.sweeps):
-            src, dst = (self.a, self.b) if k % 2 == 0 else (self.b, self.a)
-            last = k == self.sweeps - 1
-            if ev is not None and not last:
+        last = len(self.calls) - 1
+        for k, call in enumerate(self.calls):
+            if ev is not None and k != last:
                 ev.begin()
-            self.ctx.do_all(G.K_WJACOBI, [src], [dst], p=(1.0, self.h2),
-                            reduce=(G.R_L2, G.RV_UPDATE) if last else None,
-                            dev_result=self.res if last else None)
-            if ev is not None and not last:
+            call()
+            if ev is not None and k != last:
                 ev.end()
 
     def config(self):

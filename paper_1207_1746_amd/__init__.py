@@ -337,6 +337,14 @@ class Context:
             return res.value
         return None
 
+    def prepare_all(self, kind: int, ins: Sequence[Grid], outs: Sequence[Grid], p: Sequence[float] = (),
+                    reduce: tuple | None = None, dev_result=None) -> "PreparedAll":
+        """The same call as do_all, with its descriptors built once: calling the
+        returned object issues gscl_do_all again with unchanged arguments (for
+        loops of short launches, where building them costs as much as the
+        launch)."""
+        return PreparedAll(self, kind, ins, outs, p, reduce, dev_result)
+
     def do_line(self, kind: int, axis: int, direction: int, ins: Sequence[Grid], outs: Sequence[Grid],
                 p: Sequence[float] = ()):
         """Ordered line iteration space (do_i/j/k_inc for direction +1, _dec
@@ -433,6 +441,37 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class PreparedAll:
+    """A gscl_do_all call with prebuilt arguments (Context.prepare_all)."""
+
+    def __init__(self, ctx: Context, kind, ins, outs, p, reduce, dev_result):
+        self.sd = StencilDesc()
+        self.sd.kind = kind
+        for i, v in enumerate(p):
+            self.sd.p[i] = float(v)
+        self.grids = list(ins) + list(outs)  # keep the grids alive
+        self.hi, self.ni = _handles(ins)
+        self.ho, self.no = _handles(outs)
+        self.res = _f64(0.0)
+        self.host_result = reduce is not None and dev_result is None
+        self.rd = None
+        if reduce is not None:
+            self.rd = ReduceDesc()
+            self.rd.op, self.rd.operand = reduce[0], reduce[1]
+            self.rd.eps = reduce[2] if len(reduce) > 2 else 0.0
+            self.rd.dev_result = dev_result.data_ptr() if dev_result is not None else None
+        self.args = (ctx.handle, ctypes.byref(self.sd), self.hi, self.ni, self.ho, self.no,
+                     ctypes.byref(self.rd) if self.rd is not None else None,
+                     ctypes.byref(self.res) if self.rd is not None else None)
+        self.fn = lib().gscl_do_all
+
+    def __call__(self) -> float | None:
+        rc = self.fn(*self.args)
+        if rc != OK:
+            raise GsclError(rc, "gscl_do_all")
+        return self.res.value if self.host_result else None
 
 
 class Batch:

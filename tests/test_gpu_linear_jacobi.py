@@ -186,3 +186,39 @@ def test_wjacobi_f32_and_2d_layers(ctx):
     ctx.do_all(G.K_WJACOBI, [a], [b], p=(1.0, 1.0))
     np.testing.assert_allclose(b.numpy(), oracle.wjacobi_sweep(u2, None, 1.0, 1.0, G.PERIODIC, ndim=2)[0],
                                rtol=0, atol=1e-14 * 4 * np.abs(u2).max())
+
+
+def test_prepared_call_equals_do_all(ctx):
+    """Context.prepare_all issues the same gscl_do_all call: ten sweeps with a
+    fused update norm give the grids and norms do_all gives, host or device
+    result, and a failing call still raises."""
+    import torch
+    shape = (20, 33, 70)
+    u0 = np.random.default_rng(81).standard_normal(shape)
+    grids = {}
+    for tag in ("a", "b"):
+        grids[tag] = (ctx.grid(shape, G.F64, halo=1, data=u0), ctx.grid(shape, G.F64, halo=1))
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    calls = []
+    x, y = grids["b"]
+    for k in range(10):
+        src, dst = (x, y) if k % 2 == 0 else (y, x)
+        calls.append(ctx.prepare_all(G.K_WJACOBI, [src], [dst], p=(0.9, 0.01),
+                                     reduce=(G.R_L2, G.RV_UPDATE) if k == 9 else None))
+    dev = ctx.prepare_all(G.K_WJACOBI, [x], [y], p=(0.9, 0.01), reduce=(G.R_L2, G.RV_UPDATE), dev_result=res)
+    x0, y0 = grids["a"]
+    for k in range(10):
+        src, dst = (x0, y0) if k % 2 == 0 else (y0, x0)
+        r_ref = ctx.do_all(G.K_WJACOBI, [src], [dst], p=(0.9, 0.01),
+                           reduce=(G.R_L2, G.RV_UPDATE) if k == 9 else None)
+        r_got = calls[k]()
+        assert (r_got is None) == (k != 9)
+    assert r_got == r_ref
+    assert np.array_equal(x.numpy(), x0.numpy()) and np.array_equal(y.numpy(), y0.numpy())
+    assert dev() is None
+    ref = ctx.do_all(G.K_WJACOBI, [x0], [y0], p=(0.9, 0.01), reduce=(G.R_L2, G.RV_UPDATE))
+    torch.cuda.synchronize()
+    assert res.item() == ref
+    bad = ctx.prepare_all(G.K_WJACOBI, [x], [x], p=(0.9, 0.01))
+    with pytest.raises(G.GsclError):
+        bad()
