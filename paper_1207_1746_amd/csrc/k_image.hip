@@ -4,8 +4,13 @@
 //   lap = N + S + E + W - 4 C  (or 8-neighbour - 8 C)    (int16 out)
 //
 // Fast kernel (width a multiple of 16, 4-neighbour Laplacian): each lane owns
-// 16 consecutive pixels of a row and marches down a chunk of rows, with two
-// rows of loads in flight ahead of the row being filtered.  A 5-row
+// 16 consecutive pixels of a row and marches through a chunk of rows, with two
+// rows of loads in flight ahead of the row being filtered.  Chunks are mapped
+// to XCDs in contiguous ranges and march in alternating directions (even
+// chunks down, odd chunks up; both filters are symmetric in y), so the two
+// halo rows a chunk reads past each end are requested in the same steps as
+// the neighbouring chunk requests them as its own rows, and come from the
+// shared L2 instead of HBM.  A 5-row
 // queue holds the raw bytes (the lane's 16 plus 4 on each side), vertical
 // window sums are kept as running sums of packed 16-bit pairs (even / odd
 // byte lanes of each dword, so 32-bit adds never carry between halves), the
@@ -54,15 +59,22 @@ __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
 __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ img,
                                                   uint8_t* __restrict__ box,
                                                   int16_t* __restrict__ lap, Geo g, int cy) {
-    const int x = (blockIdx.x * 256 + threadIdx.x) * 16;
+    const int gxn = gridDim.x, gyn = gridDim.y;
+    const int tile = xcd_remap(blockIdx.x + gxn * (blockIdx.y + gyn * blockIdx.z), gxn * gyn * gridDim.z);
+    const int bx = tile % gxn, by = (tile / gxn) % gyn, z = tile / (gxn * gyn);
+    const int x = (bx * 256 + threadIdx.x) * 16;
     if (x >= g.nx) return;
-    const int y0 = blockIdx.y * cy;
+    const int y0 = by * cy;
     const int y1 = min(y0 + cy, g.ny);
-    const int z = blockIdx.z;
+    // march direction and first row; row i of the queue is ys + dir * (s + i - 2)
+    // at step s (the queue is symmetric in y, so the filters are unchanged)
+    const int dir = (by & 1) ? -1 : 1;
+    const int ys = dir > 0 ? y0 : y1 - 1;
+    const int n = y1 - y0;
 
     Row6 q[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) q[i] = load_row6(img, g, x, y0 - 2 + i, z);
+    for (int i = 0; i < 5; ++i) q[i] = load_row6(img, g, x, ys + dir * (i - 2), z);
     uint32_t VE[6], VO[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -72,10 +84,11 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
 
     // two rows in flight ahead of the one being consumed
     Row6 nxt1, nxt2;
-    if (y0 + 1 < y1) nxt1 = load_row6(img, g, x, y0 + 3, z);
-    for (int y = y0; y < y1; ++y) {
-        const bool more = y + 1 < y1;
-        if (y + 2 < y1) nxt2 = load_row6(img, g, x, y + 4, z);
+    if (1 < n) nxt1 = load_row6(img, g, x, ys + dir * 3, z);
+    for (int s = 0; s < n; ++s) {
+        const int y = ys + dir * s;
+        const bool more = s + 1 < n;
+        if (s + 2 < n) nxt2 = load_row6(img, g, x, ys + dir * (s + 4), z);
 
         // box: horizontal 5-sums of the vertical sums, columns 4k..4k+3
         uint32_t AE[5], AO[5];  // AE[k+1] = (hi VE[k], lo VE[k+1]), k = -1..3
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
             __builtin_nontemporal_store(vb, reinterpret_cast<u32x4*>(box + off));
         }
 
-        // Laplacian from rows y-1 (q[1]), y (q[2]), y+1 (q[3]); bias 1024 per half
+        // Laplacian from rows y -+ 1 (q[1], q[3]) and y (q[2]); bias 1024 per half
         uint32_t lo[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
