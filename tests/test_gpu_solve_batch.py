@@ -225,10 +225,10 @@ def test_batch_blocked_passes_equal_plain_sweeps(ctx, prec, k):
     """Jacobi slots swept as temporally blocked passes of k sweeps: the same
     iterates bit for bit as one-sweep passes (same stopping step), and alone
     equals among others."""
-    reqs = [_req(n, seed=n + 3, rid=i) for i, n in enumerate((17, 37, 45, 24))]
+    reqs = [_req(n, seed=n + 3, rid=i) for i, n in enumerate((17, 37, 45, 24, 7))]
     S = 16
-    plain = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3])
-    blocked = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3], sweeps_per_pass=k)
+    plain = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3, 1])
+    blocked = _batch_solve(ctx, reqs, prec, S, admit_at=[0, 0, 2, 3, 1], sweeps_per_pass=k)
     for i, r in enumerate(reqs):
         assert blocked[i][1]["state"] == 2
         assert blocked[i][1]["sweeps"] == plain[i][1]["sweeps"], i
