@@ -375,10 +375,11 @@ int gscl_solve(gscl_ctx *ctx, const gscl_solve_desc *sd, gscl_grid *const *x,
  *     last sweep of each step.
  *   precision GSCL_PREC_F32_IR: F32 correction sweeps with an F64 residual /
  *     update pass per step (iterative refinement).
- *   method GSCL_BATCH_RBGS (precision F64): red-black SOR sweeps in place
- *     (a red and a black colour pass each), then an F64 residual pass whose
- *     norm applies the stopping rule to the current u; omega = 0 gives each
- *     slot the optimal model-problem weight of its extents.
+ *   method GSCL_BATCH_RBGS (precision F64): red-black SOR sweeps (a red and
+ *     a black colour pass each; in place, or as blocked passes through a
+ *     second grid), then an F64 residual pass whose norm applies the stopping
+ *     rule to the current u; omega = 0 gives each slot the optimal
+ *     model-problem weight of its extents.
  * hbm_budget bounds the sum of admitted slot footprints (bytes). */
 enum { GSCL_BATCH_JACOBI = 0, GSCL_BATCH_RBGS = 1 };
 typedef struct {
@@ -391,10 +392,12 @@ typedef struct {
     size_t hbm_budget;
     int64_t max_sweeps;         /* per request; reaching it retires as not converged */
     int32_t method;             /* GSCL_BATCH_JACOBI (weighted Jacobi) or GSCL_BATCH_RBGS */
-    int32_t sweeps_per_pass;    /* Jacobi: 0 or 1 = one sweep per pass; k in 2..4 = temporally
-                                   blocked passes of k sweeps (GSCL_K_WJACOBI_TB tiles, the
-                                   same sweeps bit for bit); sweeps_per_step must then be a
-                                   multiple of 2k */
+    int32_t sweeps_per_pass;    /* 0 or 1 = one sweep (colour pass) per pass over memory;
+                                   k in 2..4 = temporally blocked passes (the blocked kinds'
+                                   tiles, the same results bit for bit): Jacobi: k sweeps,
+                                   sweeps_per_step a multiple of 2k; red-black: k colour
+                                   passes, k even, sweeps_per_step a multiple of k (one more
+                                   F64 grid per slot) */
 } gscl_batch_desc;
 typedef struct {
     int32_t state;              /* 0 free, 1 running, 2 converged, 3 failed */

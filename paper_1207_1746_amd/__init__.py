@@ -476,9 +476,10 @@ class PreparedAll:
 
 class Batch:
     """Batched multi-grid Poisson executor (gscl_batch_*).  method BATCH_JACOBI
-    sweeps weighted Jacobi (F64 or F32 refinement), optionally as temporally
-    blocked passes of sweeps_per_pass sweeps; BATCH_RBGS sweeps red-black SOR
-    in F64 (omega = 0: each slot's optimal model-problem weight)."""
+    sweeps weighted Jacobi (F64 or F32 refinement); BATCH_RBGS sweeps red-black
+    SOR in F64 (omega = 0: each slot's optimal model-problem weight).  Either
+    may run temporally blocked passes of sweeps_per_pass sweeps (Jacobi) or
+    colour passes (red-black, an even number)."""
 
     def __init__(self, ctx: Context, max_slots: int = 64, precision: int = PREC_F64,
                  sweeps_per_step: int = 32, use_graph: bool = True, omega: float = 6 / 7,

@@ -24,10 +24,12 @@
 //   colour passes (the red points, then the black ones, each reading only
 //   the other colour), then an F64 residual pass of the current u with its
 //   norm and the stopping rule.
-// * Jacobi sweeps may run as temporally blocked passes of k sweeps (the
-//   wide-ghost-zone tiles of the blocked driver, bitwise the same sweeps):
-//   each slot then also has a blocked tile range, walked by a persistent
-//   kernel of 16-wave blocks.
+// * Jacobi sweeps may run as temporally blocked passes of k sweeps, and
+//   red-black sweeps as blocked passes of k colour passes (k even, so every
+//   pass starts with the red points), ping-ponging through a second F64
+//   grid (the wide-ghost-zone tiles of the blocked driver, bitwise the same
+//   results): each slot then also has a blocked tile range, walked by a
+//   persistent kernel of 16-wave blocks.
 #include <math.h>
 #include <string.h>
 
@@ -75,7 +77,7 @@ struct BHeader {
     int total_tb_tiles;
 };
 
-enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2, MODE_RBGS = 3 };
+enum { MODE_F64 = 0, MODE_RESID = 1, MODE_F32 = 2, MODE_RBGS = 3, MODE_RBGS_TB = 4 };
 
 // slot owning global tile t (TB: of the blocked-pass tile list)
 template <bool TB = false>
@@ -153,8 +155,9 @@ __global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict_
 
 // k Jacobi sweeps per pass over the blocked tiles of every running slot:
 // F64 u -> u2 (parity 0) or back, or F32 corrections d -> d2 or back with the
-// F32 residual as right-hand side.  RED: the residual of the last sweep's
-// input, per blocked tile, into the partials.
+// F32 residual as right-hand side; MODE_RBGS_TB: k red-black colour passes
+// (red first) with the slot's weight, u -> u2 or back.  RED: the residual of
+// the last sweep's input, per blocked tile, into the partials.
 template <int MODE, bool RED>
 __global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restrict__ slots, const BState* st,
                                                            const BHeader* hdr, double* partials, int parity,
@@ -173,10 +176,10 @@ __global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restri
         a.g.pz = s.pz;
         a.g.bc = gk::BC_DIRICHLET;
         a.g.bcv = 0.0;
-        a.p[0] = omega;
+        a.p[0] = MODE == MODE_RBGS_TB ? s.omega : omega;
         a.p[1] = s.h2;
         a.p[2] = s.ih2;
-        a.p[3] = 0.0;
+        a.p[3] = 0.0;  // red-black: the first colour
         a.k = k;
         a.ntx = s.tntx;
         a.nty = s.tnty;
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restri
             a.f = s.f;
         }
         double acc = 0.0;
-        gk::tb7_tile<T, true, gk::TB_KMAX, RED, false>(a, t - s.tb_begin, acc);
+        gk::tb7_tile<T, true, gk::TB_KMAX, RED, MODE == MODE_RBGS_TB>(a, t - s.tb_begin, acc);
         if (RED) gk::block_reduce(acc, a.ra, t);
     }
 }
@@ -348,7 +351,8 @@ static size_t slot_work_bytes(const gscl_batch_desc& bd, const gscl_grid_desc& d
     const size_t pts = (size_t)d.pitch[1] * (size_t)d.n[2];
     const size_t r = [](size_t v) { return (v + 255) / 256 * 256; }(pts * 8);
     const size_t r4 = (pts * 4 + 255) / 256 * 256;
-    if (bd.method == GSCL_BATCH_RBGS) return r4;  // the residual grid only (in-place sweeps)
+    if (bd.method == GSCL_BATCH_RBGS)  // the residual grid (in-place sweeps), and for blocked passes the ping-pong grid
+        return r4 + (bd.sweeps_per_pass > 1 ? r : 0);
     return bd.precision == GSCL_PREC_F64 ? r : 3 * r4;
 }
 
@@ -381,10 +385,13 @@ extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_ba
         return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be even and >= 2");
     if (bd->sweeps_per_pass < 0 || bd->sweeps_per_pass > gk::TB_KMAX)
         return gscl_fail(GSCL_ERR_ARG, "sweeps_per_pass must be 0..%d", gk::TB_KMAX);
-    if (bd->sweeps_per_pass > 1 && bd->method != GSCL_BATCH_JACOBI)
-        return gscl_fail(GSCL_ERR_UNSUPPORTED, "blocked passes are for Jacobi batches");
-    if (bd->sweeps_per_pass > 1 && bd->sweeps_per_step % (2 * bd->sweeps_per_pass))
-        return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be a multiple of 2 * sweeps_per_pass");
+    if (bd->sweeps_per_pass > 1 && bd->method == GSCL_BATCH_RBGS && bd->sweeps_per_pass % 2)
+        return gscl_fail(GSCL_ERR_UNSUPPORTED, "red-black blocked passes take an even number of colour passes");
+    // an even pass count per step, so the step ends in u: 2k | S sweeps (Jacobi), k | S (red-black: 2S passes)
+    if (bd->sweeps_per_pass > 1 &&
+        bd->sweeps_per_step % (bd->method == GSCL_BATCH_RBGS ? bd->sweeps_per_pass : 2 * bd->sweeps_per_pass))
+        return gscl_fail(GSCL_ERR_ARG, "sweeps_per_step must be a multiple of %d",
+                         bd->method == GSCL_BATCH_RBGS ? bd->sweeps_per_pass : 2 * bd->sweeps_per_pass);
     if (!(bd->rtol > 0) || bd->max_sweeps < 1 || bd->hbm_budget < 4096)
         return gscl_fail(GSCL_ERR_ARG, "rtol, max_sweeps and hbm_budget must be positive");
     gscl_batch* b = new gscl_batch();
@@ -564,6 +571,7 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     s.omega = b->desc.omega;
     if (b->desc.method == GSCL_BATCH_RBGS) {
         s.rh = (float*)mem;
+        if (b->desc.sweeps_per_pass > 1) s.u2 = (double*)(mem + (pts * 4 + 255) / 256 * 256);
         if (s.omega == 0.0) {
             // optimal SOR weight of the model problem on this slot's box
             const double pi = 3.14159265358979323846;
@@ -618,9 +626,15 @@ static int enqueue_step(gscl_batch* b) {
     // blocked passes: one 16-wave block per CU in FP64, two in FP32
     const dim3 tgrid(b->desc.precision == GSCL_PREC_F64 ? 256 : 512), tblk(64 * gk::TB_NW);
     if (b->desc.method == GSCL_BATCH_RBGS) {
-        for (int k = 0; k < 2 * S; ++k)
-            hipLaunchKernelGGL((batch_sweep<MODE_RBGS, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
-                               b->d_partials, k & 1, 0.0);
+        if (kp > 1) {
+            for (int q = 0; q < 2 * S / kp; ++q)  // even count: the step ends in u
+                hipLaunchKernelGGL((batch_tb<MODE_RBGS_TB, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state,
+                                   b->d_hdr, b->d_partials, q & 1, 0.0, kp);
+        } else {
+            for (int k = 0; k < 2 * S; ++k)
+                hipLaunchKernelGGL((batch_sweep<MODE_RBGS, false>), grid, blk, 0, s, b->d_slots, b->d_state,
+                                   b->d_hdr, b->d_partials, k & 1, 0.0);
+        }
         hipLaunchKernelGGL((batch_sweep<MODE_RESID, true>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
                            b->d_partials, 0, 0.0);
         hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,

@@ -72,9 +72,10 @@ class SolveServer:
                  pipelined: bool = True, method: int = G.BATCH_JACOBI, sweeps_per_pass: int = 4):
         self.ctx = ctx
         self.pipelined = pipelined
-        # Jacobi sweeps run as temporally blocked passes of 4 (the same sweeps
-        # bit for bit) when the step length allows it
-        if method != G.BATCH_JACOBI or sweeps_per_step % (2 * sweeps_per_pass):
+        # sweeps run as temporally blocked passes of 4 (sweeps or colour
+        # passes; the same results bit for bit) when the step length allows it
+        period = 2 * sweeps_per_pass if method == G.BATCH_JACOBI else sweeps_per_pass
+        if sweeps_per_step % period or (method != G.BATCH_JACOBI and sweeps_per_pass % 2):
             sweeps_per_pass = 1
         self.batch = G.Batch(ctx, max_slots=max_slots, precision=precision,
                              sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,

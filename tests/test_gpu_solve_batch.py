@@ -239,10 +239,29 @@ def test_batch_blocked_passes_equal_plain_sweeps(ctx, prec, k):
         assert _oracle_rel_residual(blocked[i][0], f, r.h2) <= 1e-8 * 1.01
 
 
+@pytest.mark.parametrize("k,S", [(4, 4), (2, 6)])
+def test_batch_rbgs_blocked_equals_inplace(ctx, k, S):
+    """Red-black slots swept as blocked passes of k colour passes through a
+    second grid: the same iterates bit for bit and the same stopping sweep as
+    in-place colour passes, alone equal to among others."""
+    reqs = [_req(n, seed=n + 4, rid=i) for i, n in enumerate((21, 40, 9, 33))]
+    plain = _batch_solve(ctx, reqs, G.PREC_F64, S, admit_at=[0, 1, 1, 2], method=G.BATCH_RBGS, omega=0.0)
+    blocked = _batch_solve(ctx, reqs, G.PREC_F64, S, admit_at=[0, 1, 1, 2], method=G.BATCH_RBGS, omega=0.0,
+                           sweeps_per_pass=k)
+    for i, r in enumerate(reqs):
+        assert blocked[i][1]["state"] == 2
+        assert blocked[i][1]["sweeps"] == plain[i][1]["sweeps"], i
+        assert np.array_equal(blocked[i][0], plain[i][0]), i
+        alone = _batch_solve(ctx, [r], G.PREC_F64, S, method=G.BATCH_RBGS, omega=0.0, sweeps_per_pass=k,
+                             use_graph=False)[0]
+        assert np.array_equal(alone[0], blocked[i][0]) and alone[1]["sweeps"] == blocked[i][1]["sweeps"], i
+
+
 def test_batch_blocked_pass_errors(ctx):
     for kw, code in (({"sweeps_per_pass": 5}, G.ERR_ARG), ({"sweeps_per_pass": -1}, G.ERR_ARG),
                      ({"sweeps_per_pass": 4, "sweeps_per_step": 12}, G.ERR_ARG),
-                     ({"sweeps_per_pass": 2, "method": G.BATCH_RBGS}, G.ERR_UNSUPPORTED)):
+                     ({"sweeps_per_pass": 3, "method": G.BATCH_RBGS}, G.ERR_UNSUPPORTED),
+                     ({"sweeps_per_pass": 4, "sweeps_per_step": 6, "method": G.BATCH_RBGS}, G.ERR_ARG)):
         with pytest.raises(G.GsclError) as e:
             G.Batch(ctx, **{"sweeps_per_step": 16, **kw})
         assert e.value.code == code, kw
