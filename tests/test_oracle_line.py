@@ -6,7 +6,8 @@ do_k_dec process a line cell by cell in a fixed order, lines independent).
 * The dec order equals the inc order on the reversed line; any axis equals
   axis 2 on the transposed array (so the index bookkeeping is pinned).
 * Forward elimination + back substitution solve every line's tridiagonal
-  system: compared with numpy.linalg.solve on the dense matrix of each line.
+  system: compared with numpy.linalg.solve on the dense matrix of each line
+  (this pins tridiag_fwd and tridiag_back, which tridiag_solve composes).
 """
 import numpy as np
 import pytest

@@ -110,3 +110,19 @@ def test_diagonal_dominance_margin():
     M = _assemble(lambda e: oracle.vc13_apply(e, c, KAPPA), shp)
     off = np.abs(M).sum(axis=1) - np.abs(np.diag(M))
     assert np.all(np.diag(M) - off > 0.1)
+
+
+def test_residual_is_b_minus_assembled_operator():
+    """r = b - A x: against the densely assembled variable-coefficient matrix
+    (columns from the independent padded evaluator) on a small grid, and zero
+    up to rounding at the dense solution of A x = b."""
+    shp = (3, 4, 5)
+    c, b = W.vc13_grids(5, 4, 3, nfields=1)
+    c = [x.astype(np.float64) for x in c]
+    b = b[0]
+    M = _assemble(lambda e: _independent_apply(e, c, KAPPA), shp)
+    x = np.random.default_rng(90).standard_normal(shp)
+    r = oracle.vc13_residual(x, b, c, KAPPA)
+    np.testing.assert_allclose(r.ravel(), b.ravel() - M @ x.ravel(), rtol=0, atol=1e-13)
+    xs = np.linalg.solve(M, b.ravel()).reshape(shp)
+    assert np.abs(oracle.vc13_residual(xs, b, c, KAPPA)).max() <= 1e-13 * np.abs(b).max()
