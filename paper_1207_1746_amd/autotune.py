@@ -24,10 +24,16 @@ DEFAULT_CACHE = os.environ.get("GSCL_TILE_CACHE",
 RADIUS2 = (G.K_VC13_APPLY, G.K_VC13_JACOBI, G.K_VC13_RESID)
 
 
+BLOCKED = (G.K_WJACOBI_TB, G.K_RBGS_TB)
+
+
 def candidates(kind: int, dtype: int, nz: int) -> list[tuple[int, int, int]]:
     """Tile shapes that have an instantiated kernel for this kind and dtype."""
     if kind == G.K_IMG_BOX5_LAP:
         return [(4, 4, cy) for cy in (4, 8, 16, 32, 64)]
+    if kind in BLOCKED:
+        # fixed 16-wave block shape: only the z chunk (output planes) varies
+        return [(1, 16, cz) for cz in (1, 2, 4, 8, 16, 32, 64) if cz <= max(nz, 1)]
     if kind in RADIUS2:
         # one-field operators run NW = 4 only; shapes without a kernel are
         # skipped by the tuner (the launch reports them as unsupported)
@@ -53,17 +59,18 @@ def _arch() -> str:
         return "gfx950"
 
 
-def time_call(fn: Callable[[], None], reps: int = 10, warmup: int = 2) -> float:
-    """Mean milliseconds of fn() on the current stream (HIP events)."""
+def time_call(fn: Callable[[], None], reps: int = 10, warmup: int = 2, stream=None) -> float:
+    """Mean milliseconds of fn() with HIP events on `stream` (the stream fn
+    launches on; default the current stream)."""
     import torch
     for _ in range(warmup):
         fn()
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
-    s.record()
+    s.record(stream)
     for _ in range(reps):
         fn()
-    e.record()
+    e.record(stream)
     e.synchronize()
     return s.elapsed_time(e) / reps
 
@@ -93,7 +100,8 @@ class Tuner:
         for tile in cands:
             self.ctx.tile_set(kind, ref, tile)
             try:
-                ms = time_call(lambda: self.ctx.do_all(kind, ins, outs, p=p, terms=terms), reps=reps)
+                ms = time_call(lambda: self.ctx.do_all(kind, ins, outs, p=p, terms=terms), reps=reps,
+                               stream=self.ctx.stream)
             except G.GsclError:
                 continue
             results.append((ms, tile))

@@ -304,6 +304,25 @@ def test_serving_loop_continuous_batching(sctx):
         assert np.array_equal(alone[0], got)
 
 
+def test_autotuner_blocked_kind(ctx, tmp_path):
+    """The blocked sweep's only tunable is its z chunk: the tuner tries those,
+    installs the fastest, and the result is the one the default tile gives."""
+    from paper_1207_1746_amd import autotune as AT
+    shape = (40, 50, 90)
+    u = np.random.default_rng(3).standard_normal(shape)
+    gu = ctx.grid(shape, G.F64, halo=1, data=u)
+    go = ctx.grid(shape, G.F64, halo=1)
+    ctx.do_all(G.K_WJACOBI_TB, [gu], [go], p=(0.9, 1.0, 4))
+    ref = go.numpy()
+    t = AT.Tuner(ctx, str(tmp_path / "tiles.json"))
+    rec = t.tune(G.K_WJACOBI_TB, [gu], [go], p=(0.9, 1.0, 4), reps=2)
+    assert len(rec["tried"]) == len(AT.candidates(G.K_WJACOBI_TB, G.F64, shape[0]))
+    assert tuple(rec["tile"]) == ctx.tile_get(G.K_WJACOBI_TB, gu) and rec["tile"][:2] == [1, 16]
+    ctx.do_all(G.K_WJACOBI_TB, [gu], [go], p=(0.9, 1.0, 4))
+    assert np.array_equal(go.numpy(), ref)
+    ctx.tile_clear()
+
+
 def test_autotuner_picks_installs_and_caches(ctx, tmp_path):
     from paper_1207_1746_amd import autotune as AT
     shape = (24, 40, 200)
