@@ -291,9 +291,9 @@ int gscl_do_line(gscl_ctx *ctx, const gscl_stencil_desc *op, int axis, int dir,
  * independent.  Kinds GSCL_K_DIAMOND_RECUR and GSCL_K_GS2D; grids ndim 2, F64
  * or F32 (one type), same extents and pitches.  Outputs may not overlap
  * inputs, except that GS2D updates in[0] in place (out[0] must be in[0]).
- * One block walks the anti-diagonals of one layer, so a single large layer
- * runs on one CU; many layers run in parallel.  Asynchronous on the context
- * stream; errors as for gscl_do_line. */
+ * Executed as a tiled wavefront: one launch per anti-diagonal of 64 x 64
+ * tiles (every layer's tiles of that diagonal in parallel).  Asynchronous
+ * on the context stream; errors as for gscl_do_line. */
 int gscl_do_diamond(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in, int n_in,
                     gscl_grid *const *out, int n_out);
 

@@ -3,6 +3,7 @@
 // HIP graph capture of library launches.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>

@@ -50,8 +50,8 @@ struct LineArgs {
 };
 hipError_t launch_line(LineArgs& a, int dtype, int kind, int axis, hipStream_t s);
 
-// The diamond iteration space on 2D layers (one block per layer walking its
-// anti-diagonals); F64 (dtype 0) or F32 (dtype 1).  RECUR: in = {a, b, c},
+// The diamond iteration space on 2D layers (a tiled wavefront: one launch per
+// anti-diagonal of 64 x 64 tiles); F64 (dtype 0) or F32 (dtype 1).  RECUR: in = {a, b, c},
 // p[0] = seed.  GS2D: out = u in place, in[1] = f or null, p = {omega, h^2,
 // Dirichlet value}.
 enum { DIAMOND_RECUR = 0, DIAMOND_GS2D = 1 };
