@@ -63,6 +63,10 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
     const int tile = xcd_remap(blockIdx.x + gxn * (blockIdx.y + gyn * blockIdx.z), gxn * gyn * gridDim.z);
     const int bx = tile % gxn, by = (tile / gxn) % gyn, z = tile / (gxn * gyn);
     const int x = (bx * 256 + threadIdx.x) * 16;
+    // all 64 lanes of this wave inside the row (wave-uniform): only such waves
+    // exchange data between lanes for their stores; lanes past the row's end
+    // exist only in the last, partial wave
+    const bool full_wave = (bx * 256 + (int)(threadIdx.x & ~63u)) * 16 + 64 * 16 <= g.nx;
     if (x >= g.nx) return;
     const int y0 = by * cy;
     const int y1 = min(y0 + cy, g.ny);
@@ -129,7 +133,29 @@ __global__ __launch_bounds__(256) void image_fast(const uint8_t* __restrict__ im
             lo[2 * k] = pk_sub16(__builtin_amdgcn_perm(lq, le, 0x05040100u), 0x04000400u);
             lo[2 * k + 1] = pk_sub16(__builtin_amdgcn_perm(lq, le, 0x07060302u), 0x04000400u);
         }
-        {
+        if (full_wave) {
+            // each lane holds 32 contiguous bytes of the wave's 2 KB int16 row
+            // segment; exchange 16-byte halves so that each of the two stores
+            // writes 1 KB contiguously (lane t: bytes 16t and 1024 + 16t), so
+            // streaming stores never leave half-written lines
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            const int lane = threadIdx.x & 63, src = lane >> 1;
+            const bool hi = lane & 1;
+            uint32_t s0[4], s1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a0 = (uint32_t)__shfl((int)lo[k], src), b0 = (uint32_t)__shfl((int)lo[4 + k], src);
+                const uint32_t a1 = (uint32_t)__shfl((int)lo[k], src + 32), b1 = (uint32_t)__shfl((int)lo[4 + k], src + 32);
+                s0[k] = hi ? b0 : a0;
+                s1[k] = hi ? b1 : a1;
+            }
+            // first pixel of the wave's segment: lane 0's x
+            const int64_t woff = off - (int64_t)lane * 16;
+            u32x4* lp = reinterpret_cast<u32x4*>(lap + woff);
+            u32x4 l0 = {s0[0], s0[1], s0[2], s0[3]}, l1 = {s1[0], s1[1], s1[2], s1[3]};
+            __builtin_nontemporal_store(l0, lp + lane);
+            __builtin_nontemporal_store(l1, lp + 64 + lane);
+        } else {
             typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
             u32x4* lp = reinterpret_cast<u32x4*>(lap + off);
             u32x4 l0 = {lo[0], lo[1], lo[2], lo[3]}, l1 = {lo[4], lo[5], lo[6], lo[7]};
