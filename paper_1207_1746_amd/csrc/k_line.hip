@@ -100,9 +100,7 @@ __global__ __launch_bounds__(256) void line_kernel(LineArgs a) {
 // inputs are requested before the current one is walked.  Rows are padded by
 // one element in LDS so the per-line walk (lanes on different rows, same
 // column) spreads over the banks.
-constexpr int LX = 256;
-
-template <class T, int KIND, int CH>
+template <class T, int KIND, int CH, int LX>
 __global__ __launch_bounds__(LX) void line_x_kernel(LineArgs a) {
     constexpr int NI = KIND == LINE_TRIDIAG_FWD ? 4 : 2;
     constexpr int NO = KIND == LINE_TRIDIAG_FWD ? 2 : 1;
@@ -200,12 +198,13 @@ static hipError_t run_line(LineArgs& a, int axis, hipStream_t s) {
     if (axis == 2) hipLaunchKernelGGL((line_kernel<T, KIND, 2>), dim3(blocks), dim3(256), 0, s, a);
     else if (axis == 1) hipLaunchKernelGGL((line_kernel<T, KIND, 1>), dim3(blocks), dim3(256), 0, s, a);
     else {
-        // 16 cells per chunk (FP32: 64-byte row segments; FP64: 128 bytes,
-        // but 8 cells for the four-input elimination, whose LDS tile would
-        // otherwise leave one block per CU)
-        constexpr int CH = sizeof(T) == 8 && KIND == LINE_TRIDIAG_FWD ? 8 : 16;
+        // 16 cells per chunk: whole 128-byte row segments in FP64 (8-cell,
+        // half-line segments made the four-input elimination read and write
+        // each line two to four times); 256 lines per block, 128 for the
+        // elimination, whose 16-cell LDS tile is twice as large (measured)
+        constexpr int CH = 16, LX = KIND == LINE_TRIDIAG_FWD ? 128 : 256;
         const unsigned xb = (unsigned)((n + LX - 1) / LX);
-        hipLaunchKernelGGL((line_x_kernel<T, KIND, CH>), dim3(xb), dim3(LX), 0, s, a);
+        hipLaunchKernelGGL((line_x_kernel<T, KIND, CH, LX>), dim3(xb), dim3(LX), 0, s, a);
     }
     return hipGetLastError();
 }
