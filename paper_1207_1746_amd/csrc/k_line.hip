@@ -198,11 +198,11 @@ static hipError_t run_line(LineArgs& a, int axis, hipStream_t s) {
     if (axis == 2) hipLaunchKernelGGL((line_kernel<T, KIND, 2>), dim3(blocks), dim3(256), 0, s, a);
     else if (axis == 1) hipLaunchKernelGGL((line_kernel<T, KIND, 1>), dim3(blocks), dim3(256), 0, s, a);
     else {
-        // 16 cells per chunk: whole 128-byte row segments in FP64 (8-cell,
+        // whole 128-byte row segments per chunk (16 FP64 or 32 FP32 cells:
         // half-line segments made the four-input elimination read and write
         // each line two to four times); 256 lines per block, 128 for the
-        // elimination, whose 16-cell LDS tile is twice as large (measured)
-        constexpr int CH = 16, LX = KIND == LINE_TRIDIAG_FWD ? 128 : 256;
+        // elimination, whose LDS tile is twice as large (measured)
+        constexpr int CH = 128 / (int)sizeof(T), LX = KIND == LINE_TRIDIAG_FWD ? 128 : 256;
         const unsigned xb = (unsigned)((n + LX - 1) / LX);
         hipLaunchKernelGGL((line_x_kernel<T, KIND, CH, LX>), dim3(xb), dim3(LX), 0, s, a);
     }
