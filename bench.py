@@ -882,7 +882,7 @@ def main():
         print(kernel_hash(WORKLOADS[args.config].key))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (the multi-GPU path is not implemented); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
