@@ -837,6 +837,32 @@ class KernelEvents:
         return sum(ts) / len(ts) if ts else float("nan"), len(ts)
 
 
+def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=10):
+    """Read+write rate of a plain device-to-device copy of `nbytes` on the
+    same GPU (torch's copy kernel, HIP events around each copy): the HBM rate
+    a simple streaming kernel reaches on this particular device, beside the
+    published peak.  Measured after the timed steps."""
+    import torch
+    with torch.cuda.stream(stream):
+        x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            y.copy_(x)
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            y.copy_(x)
+            b.record(stream)
+            ts.append((a, b))
+    sync()
+    ms = sorted(a.elapsed_time(b) for a, b in ts)[reps // 2]
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def serve_main(args, ctx, wl):
     wl.step()  # warm-up: builds the graph, pages in kernels
     t0 = time.perf_counter()
@@ -917,6 +943,7 @@ def main():
     achieved = per_launch_bytes / (kmean_ms * 1e-3) / 1e9
     traffic = measured_traffic(wl.key)
 
+    copy_gbs = copy_bandwidth_gbs(stream)
     if args.copy_calibration:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
@@ -952,6 +979,8 @@ def main():
             "launches_timed": nk,
             "launch_sampling": f"HIP events around 1 of every {ev.stride} launches of the kernel",
             "alg_bytes_per_launch": per_launch_bytes,
+            "copy_gbs_same_gpu": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "cpu_baseline": None,
     }
