@@ -148,9 +148,12 @@ int ensure_partials(gscl_ctx* c, int64_t nblocks) {
         return gscl_fail(GSCL_ERR_NOMEM, "reduction needs %lld partials (have %lld); call gscl_reserve before capture",
                          (long long)nblocks, (long long)c->partial_cap);
     GSCL_HIP(hipStreamSynchronize(c->stream));
+    const int64_t cap = std::max<int64_t>(nblocks, 2 * c->partial_cap);
     if (c->partials) GSCL_HIP(hipFree(c->partials));
+    // until the new buffer exists the context holds none (a failed
+    // allocation leaves capacity 0, so the next reduction retries it)
     c->partials = nullptr;
-    int64_t cap = std::max<int64_t>(nblocks, 2 * c->partial_cap);
+    c->partial_cap = 0;
     GSCL_HIP(hipMalloc(&c->partials, (size_t)cap * sizeof(double)));
     c->partial_cap = cap;
     return GSCL_OK;

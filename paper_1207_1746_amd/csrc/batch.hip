@@ -509,13 +509,17 @@ static int upload_table(gscl_batch* b) {
     if (need > b->partial_cap) {
         // grow the partials (invalidates a captured step graph)
         GSCL_HIP(hipStreamSynchronize(c->stream));
-        GSCL_HIP(hipFree(b->d_partials));
-        b->partial_cap = std::max<int64_t>(need, 2 * b->partial_cap);
-        GSCL_HIP(hipMalloc(&b->d_partials, sizeof(double) * b->partial_cap));
+        const int64_t cap = std::max<int64_t>(need, 2 * b->partial_cap);
         if (b->graph) {
             gscl_graph_destroy(b->graph);
             b->graph = nullptr;
         }
+        GSCL_HIP(hipFree(b->d_partials));
+        // a failed allocation leaves capacity 0: the next upload retries it
+        b->d_partials = nullptr;
+        b->partial_cap = 0;
+        GSCL_HIP(hipMalloc(&b->d_partials, sizeof(double) * cap));
+        b->partial_cap = cap;
     }
     b->h_hdr->nslots = n;
     b->h_hdr->total_tiles = tiles;
