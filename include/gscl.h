@@ -52,7 +52,7 @@ enum {
     GSCL_ERR_NOCONV = -8,       /* solver hit max_sweeps before rtol */
     GSCL_ERR_HIP = -9,          /* a HIP runtime call failed (message has the HIP error) */
     GSCL_ERR_NUMERIC = -10,     /* NaN/Inf met by a solver */
-    GSCL_ERR_UNSUPPORTED = -11  /* valid request this build has no kernel for */
+    GSCL_ERR_UNSUPPORTED = -11  /* valid request the library has no kernel for */
 };
 
 /* ---- element types, boundary rules -------------------------------------- */
