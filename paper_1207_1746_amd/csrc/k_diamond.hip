@@ -12,10 +12,14 @@ namespace gk {
 // anti-diagonal D = I + J.  Tile (I, J) reads only tiles (I-1, J) and
 // (I, J-1), finished by earlier launches (the new W and S values), and
 // (I+1, J), (I, J+1), which later launches change (the old E and N values);
-// never a tile of its own diagonal, so those run in parallel.  One wave owns a
-// tile: it loads the tile and its one-cell halo into LDS with row-contiguous
-// accesses (eight rows in flight), walks the tile's anti-diagonals, and
-// stores the tile back.  In the walk lane t owns column t: cell (t, j) is
+// never a tile of its own diagonal, so those run in parallel.  A block of
+// DNW waves owns a tile: the waves load the tile and its one-cell halo into
+// LDS with row-contiguous accesses (each wave eight rows in flight, the waves
+// on interleaved row batches), the first wave alone walks the tile's
+// anti-diagonals, and all waves store the tile back.  (One wave per tile
+// left the loads and stores latency-bound: a tile's LDS footprint allows
+// one to four blocks per CU; 8 waves ran 1.5-1.6 times faster, 16 no faster
+// than 8.)  In the walk lane t owns column t: cell (t, j) is
 // computed at step t + j from its S neighbour (the lane's own previous
 // result) and its W neighbour (lane t-1's previous result, by a wave-wide DPP
 // shift), so the dependency chain never goes through LDS.  During the walk
@@ -24,7 +28,7 @@ namespace gk {
 // only its lane reads, once, just before: so the walk needs no barrier.  The
 // per-cell arithmetic is the operators' above, in the same order.  Rows are 66 elements apart in LDS, so lanes on different rows of
 // the same anti-diagonal spread over the banks.
-constexpr int DT = 64;
+constexpr int DT = 64, DNW = 8;
 
 // value of lane t-1 (lane 0 gets 0): wave_shr:1
 __device__ __forceinline__ float from_lane_below(float v) {
@@ -38,13 +42,13 @@ __device__ __forceinline__ double from_lane_below(double v) {
 }
 
 template <class T, int KIND>
-__global__ __launch_bounds__(64) void diamond_tile(DiamondArgs a, int D, int i_lo, int count) {
+__global__ __launch_bounds__(64 * DNW) void diamond_tile(DiamondArgs a, int D, int i_lo, int count) {
 #pragma clang fp contract(off)
     constexpr int LW = DT + 2, RB = 8;
     constexpr int NP = KIND == DIAMOND_RECUR ? 3 : 1;  // pointwise inputs: a, b, c or f
     __shared__ T U[LW][LW];         // the tile's values with a one-cell halo ring
     __shared__ T P[NP][DT][DT];     // pointwise inputs of the tile's cells; P[0] then the results
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int I = i_lo + (int)(blockIdx.x % (unsigned)count), J = D - I;
     const int64_t base = (int64_t)(blockIdx.x / (unsigned)count) * a.pz;
     const int nx = a.nx, ny = a.ny;
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(64) void diamond_tile(DiamondArgs a, int D, int i_l
     // load: halo ring from the grid being computed (W and S new, E and N old;
     // GS2D also the tile's own old values), pointwise inputs of the cells.
     // Columns t and t + 64 of LDS rows r0 .. r0 + RB - 1 per batch.
-    for (int r0 = 0; r0 < th + 2; r0 += RB) {
+    for (int r0 = w * RB; r0 < th + 2; r0 += DNW * RB) {
         T uv[RB][2], pv[RB][NP];
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
@@ -100,18 +104,19 @@ __global__ __launch_bounds__(64) void diamond_tile(DiamondArgs a, int D, int i_l
     const T omega = (T)a.p[0], h2 = (T)a.p[1];
     const int c = t + 1;
     T last = T(0);  // this lane's result at the previous step (its next cell's S)
-    for (int d = 0; d <= tw + th - 2; ++d) {
+    // the walk: first wave only (the others wait at the barrier below)
+    for (int d = 0; d <= (w == 0 ? tw + th - 2 : -1); ++d) {
         const T wl = from_lane_below(last);  // lane t-1's previous result (every lane shifts)
         const int jl = d - t;
         if (t < tw && jl >= 0 && jl < th) {
             const int r = jl + 1;
-            const T w = t == 0 ? U[r][0] : wl;
+            const T wv = t == 0 ? U[r][0] : wl;
             const T sv = jl == 0 ? U[0][c] : last;
             T res;
             if (KIND == DIAMOND_RECUR) {
-                res = P[0][jl][t] * w + P[1][jl][t] * sv + P[2][jl][t];
+                res = P[0][jl][t] * wv + P[1][jl][t] * sv + P[2][jl][t];
             } else {
-                T sum = w + sv;
+                T sum = wv + sv;
                 sum = sum + U[r][c + 1];
                 sum = sum + U[r + 1][c];
                 res = (T(1) - omega) * U[r][c] + omega * ((sum - h2 * P[0][jl][t]) / T(4));
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(64) void diamond_tile(DiamondArgs a, int D, int i_l
     }
     __syncthreads();
     if (t < tw) {
-        for (int r = 1; r <= th; ++r) out[base + (int64_t)(y0 - 1 + r) * py + (x0 + t)] = P[0][r - 1][t];
+        for (int r = 1 + w; r <= th; r += DNW) out[base + (int64_t)(y0 - 1 + r) * py + (x0 + t)] = P[0][r - 1][t];
     }
 }
 
@@ -132,7 +137,7 @@ static hipError_t run_tiled(DiamondArgs& a, hipStream_t s) {
     for (int D = 0; D <= ntx + nty - 2; ++D) {
         const int i_lo = std::max(0, D - (nty - 1)), i_hi = std::min(D, ntx - 1);
         const int count = i_hi - i_lo + 1;
-        hipLaunchKernelGGL((diamond_tile<T, KIND>), dim3((unsigned)count * (unsigned)a.nl), dim3(64), 0, s, a, D,
+        hipLaunchKernelGGL((diamond_tile<T, KIND>), dim3((unsigned)count * (unsigned)a.nl), dim3(64 * DNW), 0, s, a, D,
                            i_lo, count);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
