@@ -36,9 +36,11 @@ def test_diamond_recur_matches_oracle(ctx, shape, dt):
         assert np.abs(got - ex).max() <= 256 * 2.0 ** -24 * (np.abs(ex).max() + 1)
 
 
+# shapes: one partial tile; whole 64 x 64 tiles (every row batch of the
+# tile's waves full); 2 x 3 tiles with 2-row and 3-column ragged tails
+@pytest.mark.parametrize("shape", [(4, 45, 70), (2, 64, 128), (1, 130, 131)])
 @pytest.mark.parametrize("dt", [G.F64, G.F32])
-def test_gs2d_sweeps_match_oracle(ctx, dt):
-    shape = (4, 45, 70)
+def test_gs2d_sweeps_match_oracle(ctx, dt, shape):
     g = np.random.default_rng(71)
     u = g.standard_normal(shape)
     f = g.standard_normal(shape)
