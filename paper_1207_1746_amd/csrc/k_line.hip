@@ -198,11 +198,12 @@ static hipError_t run_line(LineArgs& a, int axis, hipStream_t s) {
     if (axis == 2) hipLaunchKernelGGL((line_kernel<T, KIND, 2>), dim3(blocks), dim3(256), 0, s, a);
     else if (axis == 1) hipLaunchKernelGGL((line_kernel<T, KIND, 1>), dim3(blocks), dim3(256), 0, s, a);
     else {
-        // whole 128-byte row segments per chunk (16 FP64 or 32 FP32 cells:
-        // half-line segments made the four-input elimination read and write
-        // each line two to four times); 256 lines per block, 128 for the
-        // elimination, whose LDS tile is twice as large (measured)
-        constexpr int CH = 128 / (int)sizeof(T), LX = KIND == LINE_TRIDIAG_FWD ? 128 : 256;
+        // 32-cell chunks: whole 128-byte (FP32) or 256-byte (FP64) row
+        // segments (half-line segments made the four-input elimination read
+        // and write each line two to four times; FP64 16-cell chunks ran
+        // 2-8% slower); 128 lines per block, 256 for the FP32 recurrence and
+        // substitution, whose LDS tile is smallest (measured)
+        constexpr int CH = 32, LX = (sizeof(T) == 8 || KIND == LINE_TRIDIAG_FWD) ? 128 : 256;
         const unsigned xb = (unsigned)((n + LX - 1) / LX);
         hipLaunchKernelGGL((line_x_kernel<T, KIND, CH, LX>), dim3(xb), dim3(LX), 0, s, a);
     }
