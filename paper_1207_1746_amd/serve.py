@@ -34,7 +34,8 @@ class Job:
     done_at: float | None = None
     sweeps: int = 0
     rel_residual: float = float("nan")
-    state: int = 0
+    state: int = 0            # 0 queued/running, 2 converged, 3 rejected or failed
+    error: str = ""
 
 
 @dataclass
@@ -46,7 +47,7 @@ class ServeReport:
     occupancy: list = field(default_factory=list)
 
     def latencies(self):
-        return sorted(j.done_at - j.arrival for j in self.jobs if j.done_at is not None)
+        return sorted(j.done_at - j.arrival for j in self.jobs if j.done_at is not None and j.state == 2)
 
     def summary(self) -> dict:
         lat = self.latencies()
@@ -59,6 +60,7 @@ class ServeReport:
 
         done = [j for j in self.jobs if j.state == 2]
         return {"requests": len(self.jobs), "converged": len(done),
+                "rejected": sum(1 for j in self.jobs if j.state == 3),
                 "solves_per_s": len(done) / self.wall if self.wall > 0 else float("nan"),
                 "p50_s": pct(50), "p99_s": pct(99), "wall_s": self.wall, "steps": self.steps,
                 "max_running": self.max_running,
@@ -81,6 +83,15 @@ class SolveServer:
                              sweeps_per_step=sweeps_per_step, use_graph=use_graph, omega=omega,
                              rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps, method=method,
                              sweeps_per_pass=sweeps_per_pass)
+        self.hbm_budget = hbm_budget
+
+    def _reject(self, job: Job, now: float, why: str):
+        job.state = 3
+        job.error = why
+        job.done_at = now
+        if job.u is not None:
+            job.u.close()
+            job.u = None
 
     def _admit(self, job: Job, now: float) -> bool:
         shape = (job.n, job.n, job.n)
@@ -109,10 +120,19 @@ class SolveServer:
         while i < len(pending) or queue or running:
             now = time.perf_counter() - t0
             while i < len(pending) and (not realtime or pending[i].arrival <= now):
-                queue.append(pending[i])
+                job = pending[i]
                 i += 1
+                fp = self.batch.footprint((job.n, job.n, job.n))
+                if fp > self.hbm_budget:
+                    self._reject(job, now, f"footprint {fp} bytes exceeds the HBM budget {self.hbm_budget}")
+                    continue
+                queue.append(job)
             while queue:
                 if not self._admit(queue[0], now):
+                    if not running:
+                        # an empty batch cannot take it either: it never will
+                        self._reject(queue.pop(0), now, G.lib().gscl_last_error().decode(errors="replace"))
+                        continue
                     break
                 job = queue.pop(0)
                 running[job.slot] = job

@@ -2,8 +2,9 @@
 benchmark uses, via checks the oracle can afford at any size.
 
 * 13-point operator on 5 fields at 512^3: the first and last fields of the
-  BF16 apply against the full FP64 oracle apply; iterative refinement in BF16 storage to 1e-10
-  with the FP64 residual of every field recomputed by the oracle.
+  BF16 apply against the full FP64 oracle apply; iterative refinement with
+  BF16, FP16 and FP32 storage to 1e-10 with the FP64 residual of every field
+  recomputed by the oracle.
 * Poisson solves at N = 192 (the largest request size): the residual trace of
   weighted Jacobi on a sum of distinct sine modes is closed form,
   ||r_n||^2 = sum_m a_m^2 lambda_m^2 rho_m^(2n) ||phi||^2, which predicts the
@@ -39,22 +40,29 @@ def test_vc13_512_apply_bf16(ctx):
         assert np.abs(got - ex).max() <= tol, f
 
 
-def test_vc13_512_refinement_bf16_reaches_1e10(sctx):
+@pytest.mark.parametrize("prec,dt", [(G.PREC_BF16_IR, G.BF16), (G.PREC_F16_IR, G.F16),
+                                     (G.PREC_F32_IR, G.F32)])
+def test_vc13_512_refinement_reaches_1e10(sctx, prec, dt):
+    """Refinement with the correction grids stored in BF16, FP16 or FP32 (FP32
+    math) to 1e-10: the oracle recomputes every field's FP64 residual."""
     ctx = sctx
     n, nf = 512, 5
     c, b = W.vc13_grids(n, nfields=nf)
     shp = (n, n, n)
     gx = [ctx.grid(shp, G.F64, halo=2).fill(0.0) for _ in range(nf)]
     gb = [ctx.grid(shp, G.F64, halo=0, data=x) for x in b]
-    gc = [ctx.grid(shp, G.BF16, halo=0, data=x) for x in c]
+    gc = [ctx.grid(shp, dt, halo=0, data=x) for x in c]
     st = ctx.solve(G.K_VC13_APPLY, gx, gb, gc, kappa=W.VC13_KAPPA, rtol=1e-10, check_every=8,
-                   precision=G.PREC_BF16_IR, inner_sweeps=16)
+                   precision=prec, inner_sweeps=16)
+    del gc
     bn2 = sum(oracle.sumsq(x) for x in b)
-    rn2 = 0.0
+    per_field = []
     for f in range(nf):
-        rn2 += oracle.sumsq(oracle.vc13_residual(gx[f].numpy(), b[f], c, W.VC13_KAPPA))
-    assert math.sqrt(rn2 / bn2) <= 1e-10 * 1.001, st
-    assert abs(math.sqrt(rn2 / bn2) - st["rel_residual"]) <= 1e-3 * st["rel_residual"]
+        per_field.append(oracle.sumsq(oracle.vc13_residual(gx[f].numpy(), b[f], c, W.VC13_KAPPA)))
+        gx[f].close()
+    rel = math.sqrt(sum(per_field) / bn2)
+    assert rel <= 1e-10 * 1.001, (st, [math.sqrt(r / oracle.sumsq(x)) for r, x in zip(per_field, b)])
+    assert abs(rel - st["rel_residual"]) <= 1e-3 * st["rel_residual"]
 
 
 def _predicted_stop(req, S, rtol, omega=6 / 7):

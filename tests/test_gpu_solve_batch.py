@@ -115,10 +115,10 @@ def test_vc13_solve_per_precision(ctx, prec, dt):
 
 
 def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8, method=G.BATCH_JACOBI,
-                 omega=6 / 7, sweeps_per_pass=1):
+                 omega=6 / 7, sweeps_per_pass=1, hbm_budget=1 << 30):
     """Run requests through one batch; admit_at[i] = step index to admit request i."""
     b = G.Batch(ctx, max_slots=8, precision=prec, sweeps_per_step=S, use_graph=use_graph, rtol=rtol,
-                hbm_budget=1 << 30, method=method, omega=omega, sweeps_per_pass=sweeps_per_pass)
+                hbm_budget=hbm_budget, method=method, omega=omega, sweeps_per_pass=sweeps_per_pass)
     admit_at = admit_at or [0] * len(reqs)
     grids = {}
     out = {}
@@ -239,6 +239,29 @@ def test_batch_blocked_passes_equal_plain_sweeps(ctx, prec, k):
         assert _oracle_rel_residual(blocked[i][0], f, r.h2) <= 1e-8 * 1.01
 
 
+def test_batch_f32_refinement_large_slots_1e10(ctx):
+    """The served configuration at the large end of the request sizes: F32
+    refinement with blocked passes of 4 sweeps, steps of 64 sweeps, three
+    slots of N in [150, 192] among small ones, to 1e-10.  Every answer's FP64
+    residual is recomputed by the oracle, and each request alone gives the
+    same answer bit for bit as in the mix."""
+    sizes = (150, 24, 171, 37, 192, 61)
+    reqs = [_req(n, seed=n + 7, rid=i) for i, n in enumerate(sizes)]
+    S, k, rtol = 64, 4, 1e-10
+    mix = _batch_solve(ctx, reqs, G.PREC_F32_IR, S, admit_at=[0, 0, 1, 2, 3, 5], rtol=rtol,
+                       sweeps_per_pass=k, hbm_budget=4 << 30)
+    for i, r in enumerate(reqs):
+        assert mix[i][1]["state"] == 2, (r.n, mix[i][1])
+        _, f = W.poisson_fields(r)
+        rel = _oracle_rel_residual(mix[i][0], f, r.h2)
+        assert rel <= rtol * 1.01, (r.n, rel, mix[i][1])
+        if r.n >= 150:
+            alone = _batch_solve(ctx, [r], G.PREC_F32_IR, S, rtol=rtol, sweeps_per_pass=k,
+                                 hbm_budget=4 << 30)[0]
+            assert np.array_equal(alone[0], mix[i][0]), r.n
+            assert alone[1]["sweeps"] == mix[i][1]["sweeps"], r.n
+
+
 @pytest.mark.parametrize("k,S", [(4, 4), (2, 6)])
 def test_batch_rbgs_blocked_equals_inplace(ctx, k, S):
     """Red-black slots swept as blocked passes of k colour passes through a
@@ -343,3 +366,33 @@ def test_autotuner_picks_installs_and_caches(ctx, tmp_path):
     t2 = AT.Tuner(ctx, path)
     assert t2.apply(G.K_WJACOBI, gu) and ctx.tile_get(G.K_WJACOBI, gu) == tuple(rec["tile"])
     ctx.tile_clear()
+
+
+@pytest.mark.timeout(60)
+def test_serving_rejects_request_that_never_fits(sctx):
+    """A request whose footprint exceeds the whole budget is reported as
+    rejected instead of waiting in the queue for ever; the loop returns and
+    serves the others."""
+    ctx = sctx
+    reqs = W.poisson_requests(count=4, qps=float("inf"), nmin=12, nmax=20, seed_index=9)
+    big = _req(48, seed=5, rid=99)
+    jobs = []
+    for r in reqs[:2] + [big] + reqs[2:]:
+        _, f = W.poisson_fields(r)
+        jobs.append(SV.Job(r.rid, r.n, r.h2, 0.0, f))
+    probe = G.Batch(ctx, max_slots=1, precision=G.PREC_F64, sweeps_per_step=8, hbm_budget=1 << 30)
+    fp_small = max(probe.footprint((r.n,) * 3) for r in reqs)
+    fp_big = probe.footprint((48,) * 3)
+    probe.close()
+    assert fp_big > 2 * fp_small
+    srv = SV.SolveServer(ctx, precision=G.PREC_F64, sweeps_per_step=16, rtol=1e-8, max_slots=4,
+                         hbm_budget=2 * fp_small, sweeps_per_pass=1)
+    rep = srv.run(jobs, realtime=False)
+    srv.close()
+    s = rep.summary()
+    assert s["rejected"] == 1 and s["converged"] == len(reqs)
+    rej = [j for j in jobs if j.state == 3]
+    assert rej[0].rid == 99 and "budget" in rej[0].error and rej[0].u is None
+    for j, r in zip([j for j in jobs if j.state == 2], reqs):
+        _, f = W.poisson_fields(r)
+        assert _oracle_rel_residual(j.u.numpy(), f, r.h2) <= 1e-8 * 1.01
