@@ -25,9 +25,10 @@
  *     return a host scalar (do_reduce / fused reductions without a device
  *     result pointer, solve, batch_poll, end), which synchronize the stream.
  *   - One context per host thread.  Contexts on one device may share grids.
- *   - The library never allocates in gscl_do_all / gscl_do_reduce /
- *     gscl_batch_step: scratch is reserved by gscl_begin and grows only in
- *     gscl_reserve, so these calls may be captured into a HIP graph.
+ *   - gscl_do_reduce and gscl_batch_step never allocate.  gscl_do_all
+ *     allocates only when a fused reduction needs more block partials than
+ *     gscl_begin / gscl_reserve set aside (inside graph capture it fails with
+ *     GSCL_ERR_NOMEM instead); gscl_do_all_noalloc never allocates.
  */
 #ifndef GSCL_H
 #define GSCL_H
@@ -273,6 +274,23 @@ int gscl_grid_destroy(gscl_grid *grid);
 int gscl_do_all(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in, int n_in,
                 gscl_grid *const *out, int n_out, const gscl_reduce_desc *fused,
                 double *fused_result);
+/* Allocation-free do_all, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid it).
+ * Same operators, arguments, validation, kernels and results as gscl_do_all
+ * (bit for bit); a fused reduction keeps its block partials and its result
+ * slot in a fixed device array of the library (GSCL_NOALLOC_PARTIALS partials
+ * + 64 slots, ~0.5 MB, held on each device the library runs on until the
+ * process ends) instead of the context's buffers, and the call never calls
+ * hipMalloc or hipFree.  A fused reduction over more blocks than
+ * GSCL_NOALLOC_PARTIALS returns GSCL_ERR_NOMEM (gscl_do_all serves it).
+ * Every call on one device shares that array: calls that overlap on one
+ * device (several streams, threads or contexts) race and must be ordered by
+ * the caller.  Nothing in the array needs clearing between calls. */
+#define GSCL_NOALLOC_PARTIALS 65536
+int gscl_do_all_noalloc(gscl_ctx *ctx, const gscl_stencil_desc *op, gscl_grid *const *in,
+                        int n_in, gscl_grid *const *out, int n_out,
+                        const gscl_reduce_desc *fused, double *fused_result);
+
 /* Ordered line iteration spaces (Section 3: do_i_inc, do_j_inc, do_k_inc and
  * do_i_dec, do_j_dec, do_k_dec): every line of the grids along `axis`
  * (0 = i / x, 1 = j / y, 2 = k / z, which needs ndim 3) is processed cell by

@@ -92,6 +92,8 @@ _SIGS = {
     "gscl_grid_destroy": (ctypes.c_int, [_vp]),
     "gscl_do_all": (ctypes.c_int, [_vp, _P(StencilDesc), _P(_vp), ctypes.c_int, _P(_vp), ctypes.c_int,
                                    _P(ReduceDesc), _P(_f64)]),
+    "gscl_do_all_noalloc": (ctypes.c_int, [_vp, _P(StencilDesc), _P(_vp), ctypes.c_int, _P(_vp), ctypes.c_int,
+                                           _P(ReduceDesc), _P(_f64)]),
     "gscl_do_line": (ctypes.c_int, [_vp, _P(StencilDesc), ctypes.c_int, ctypes.c_int, _P(_vp), ctypes.c_int,
                                     _P(_vp), ctypes.c_int]),
     "gscl_do_diamond": (ctypes.c_int, [_vp, _P(StencilDesc), _P(_vp), ctypes.c_int, _P(_vp), ctypes.c_int]),
@@ -302,9 +304,11 @@ class Context:
     # iteration spaces ---------------------------------------------------------
     def do_all(self, kind: int, ins: Sequence[Grid], outs: Sequence[Grid], p: Sequence[float] = (),
                terms: Sequence[tuple] | None = None, reduce: tuple | None = None,
-               dev_result=None) -> float | None:
+               dev_result=None, noalloc: bool = False) -> float | None:
         """reduce = (op, operand[, eps]); returns the host result unless dev_result
-        (a device double tensor element) is given."""
+        (a device double tensor element) is given.  noalloc=True issues
+        gscl_do_all_noalloc (fused-reduction scratch in the library's fixed
+        device array)."""
         sd = StencilDesc()
         sd.kind = kind
         for i, v in enumerate(p):
@@ -329,10 +333,11 @@ class Context:
             rd.eps = reduce[2] if len(reduce) > 2 else 0.0
             rd.dev_result = dev_result.data_ptr() if dev_result is not None else None
             rd_p = ctypes.byref(rd)
-        rc = lib().gscl_do_all(self.handle, ctypes.byref(sd), hi, ni, ho, no, rd_p,
-                               ctypes.byref(res) if reduce is not None else None)
+        fn = lib().gscl_do_all_noalloc if noalloc else lib().gscl_do_all
+        rc = fn(self.handle, ctypes.byref(sd), hi, ni, ho, no, rd_p,
+                ctypes.byref(res) if reduce is not None else None)
         del keep
-        check(rc, "gscl_do_all")
+        check(rc, "gscl_do_all_noalloc" if noalloc else "gscl_do_all")
         if reduce is not None and dev_result is None:
             return res.value
         return None

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "api_internal.h"
 #include "tb7.h"
@@ -159,11 +160,38 @@ int ensure_partials(gscl_ctx* c, int64_t nblocks) {
     return GSCL_OK;
 }
 
+// Fixed device scratch of the allocation-free do_all variant: block partials
+// of a fused reduction followed by one result slot.  Every kernel writes each
+// partial it later folds, so nothing has to start at zero.  Host code never
+// passes the symbol itself: its device address is looked up once per device
+// (with that device current) and kept below.
+static __device__ __align__(256) double scratch[GSCL_NOALLOC_PARTIALS + 64];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[64];
+
+static int scratch_setup(int device) {
+    if (device >= 64) return gscl_fail(GSCL_ERR_ARG, "device %d beyond the 64 the library tracks", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return GSCL_OK;
+    void* ptr = nullptr;
+    GSCL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[device] = (double*)ptr;
+    return GSCL_OK;
+}
+
+static double* scratch_of(int device) {
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
 extern "C" int gscl_begin(gscl_ctx* c, void* stream) {
     if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
     if (c->state == CTX_ACTIVE) return gscl_fail(GSCL_ERR_STATE, "context already active");
     if (c->state == CTX_FINALIZED) return gscl_fail(GSCL_ERR_STATE, "context finalized");
     GSCL_HIP(hipSetDevice(c->device));
+    int src = scratch_setup(c->device);
+    if (src) return src;
     c->stream = (hipStream_t)stream;
     if (!c->result) {
         GSCL_HIP(hipMalloc(&c->result, 64 * sizeof(double)));
@@ -374,9 +402,26 @@ static int check_dtypes(gscl_grid* const* g, int first, int count, int dt, const
     return GSCL_OK;
 }
 
-static void fill_red(gscl_ctx* c, const gscl_reduce_desc* rd, gk::RedArgs& ra) {
-    ra.partials = c->partials;
-    ra.result = rd && rd->dev_result ? (double*)rd->dev_result : c->result;
+// Where a call's reduction scratch lives: the context's growable buffers
+// (fixed == nullptr) or the library's fixed device scratch.
+struct FixedScratch {
+    double* partials;  // GSCL_NOALLOC_PARTIALS block partials
+    double* result;    // one result slot
+};
+
+static int take_partials(gscl_ctx* c, const FixedScratch* fx, int64_t nblocks) {
+    if (!fx) return ensure_partials(c, nblocks);
+    if (nblocks > GSCL_NOALLOC_PARTIALS)
+        return gscl_fail(GSCL_ERR_NOMEM,
+                         "fused reduction over %lld blocks exceeds the fixed scratch of %d partials "
+                         "(use gscl_do_all for this grid)",
+                         (long long)nblocks, GSCL_NOALLOC_PARTIALS);
+    return GSCL_OK;
+}
+
+static void fill_red(gscl_ctx* c, const gscl_reduce_desc* rd, gk::RedArgs& ra, const FixedScratch* fx = nullptr) {
+    ra.partials = fx ? fx->partials : c->partials;
+    ra.result = rd && rd->dev_result ? (double*)rd->dev_result : (fx ? fx->result : c->result);
     ra.op = rd ? rd->op : 0;
     ra.eps = rd ? rd->eps : 0.0;
 }
@@ -390,10 +435,12 @@ static int check_reduce_desc(const gscl_reduce_desc* rd, double* host_result, bo
     return GSCL_OK;
 }
 
-static int finish_reduce(gscl_ctx* c, const gscl_reduce_desc* rd, double* host_result) {
+static int finish_reduce(gscl_ctx* c, const gscl_reduce_desc* rd, double* host_result,
+                         const FixedScratch* fx = nullptr) {
     if (rd->dev_result) return GSCL_OK;
     if (c->capturing) return gscl_fail(GSCL_ERR_STATE, "host-result reduction inside graph capture");
-    GSCL_HIP(hipMemcpyAsync(host_result, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GSCL_HIP(hipMemcpyAsync(host_result, fx ? fx->result : c->result, sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
     GSCL_HIP(hipStreamSynchronize(c->stream));
     return GSCL_OK;
 }
@@ -404,8 +451,9 @@ static void fill_targs(gk::TArgs& a, const gscl_grid* geo_src, const double* p) 
     for (int i = 0; i < 8; ++i) a.p[i] = p[i];
 }
 
-extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* const* in, int n_in,
-                           gscl_grid* const* out, int n_out, const gscl_reduce_desc* fused, double* fused_result) {
+static int do_all_impl(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* const* in, int n_in,
+                       gscl_grid* const* out, int n_out, const gscl_reduce_desc* fused, double* fused_result,
+                       const FixedScratch* fx) {
     if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
     if (c->state != CTX_ACTIVE)
         return gscl_fail(GSCL_ERR_STATE, "do_all outside gscl_begin/gscl_end (context state %d)", c->state);
@@ -467,8 +515,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             la.operand = red ? fused->operand : 0;
             if (red) {
                 const int64_t nb = ((la.g.nx + 63) / 64) * (int64_t)((la.g.ny + 3) / 4) * la.g.nz;
-                if ((rc = ensure_partials(c, nb))) return rc;
-                fill_red(c, fused, la.ra);
+                if ((rc = take_partials(c, fx, nb))) return rc;
+                fill_red(c, fused, la.ra, fx);
             }
             he = gk::launch_linear(la, dt, red, c->stream, &nblocks);
             break;
@@ -489,8 +537,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             if (red) {
                 t = reduce_tile(t, g0->d);
-                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
-                fill_red(c, fused, a.ra);
+                if ((rc = take_partials(c, fx, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra, fx);
             }
             he = gk::launch_wjacobi(a, dt, g0->d.ndim, n_in == 2, t, red, c->stream, &nblocks);
             break;
@@ -517,8 +565,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             if (red) {
                 t = reduce_tile(t, g0->d);
-                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
-                fill_red(c, fused, a.ra);
+                if ((rc = take_partials(c, fx, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra, fx);
             }
             he = gk::launch_rbgs(a, dt, n_in == 2, t, red, c->stream, &nblocks);
             break;
@@ -553,8 +601,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             ta.cz = t.cz;
             if (red) {
-                if ((rc = ensure_partials(c, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
-                fill_red(c, fused, ta.ra);
+                if ((rc = take_partials(c, fx, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
+                fill_red(c, fused, ta.ra, fx);
             }
             he = gk::launch_wjacobi_tb(ta, dt == GSCL_F64 ? 0 : 1, n_in == 2, red, c->stream, &nblocks);
             break;
@@ -587,8 +635,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             ta.cz = t.cz;
             if (red) {
-                if ((rc = ensure_partials(c, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
-                fill_red(c, fused, ta.ra);
+                if ((rc = take_partials(c, fx, gk::tb_blocks(ta.g, ta.k, ta.cz)))) return rc;
+                fill_red(c, fused, ta.ra, fx);
             }
             he = gk::launch_rbgs_tb(ta, dt == GSCL_F64 ? 0 : 1, n_in == 2, red, c->stream, &nblocks);
             break;
@@ -608,8 +656,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, GSCL_K_WJACOBI, GSCL_F64, g0->d);
             if (red) {
                 t = reduce_tile(t, g0->d);
-                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
-                fill_red(c, fused, a.ra);
+                if ((rc = take_partials(c, fx, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra, fx);
             }
             he = gk::launch_poisson_resid(a, t, red, c->stream, &nblocks);
             break;
@@ -629,8 +677,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dt, g0->d);
             if (red) {
                 t = reduce_tile(t, g0->d);
-                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
-                fill_red(c, fused, a.ra);
+                if ((rc = take_partials(c, fx, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra, fx);
             }
             he = gk::launch_varcoef7(a, dt, t, red, c->stream, &nblocks);
             break;
@@ -686,8 +734,8 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
             gk::TileCfg t = pick_tile(c, op->kind, dnb, g0->d);
             if (red) {
                 t = reduce_tile(t, g0->d);
-                if ((rc = ensure_partials(c, gk::tiled_blocks(a.g, t)))) return rc;
-                fill_red(c, fused, a.ra);
+                if ((rc = take_partials(c, fx, gk::tiled_blocks(a.g, t)))) return rc;
+                fill_red(c, fused, a.ra, fx);
             }
             if (op->kind == GSCL_K_VC13_APPLY) {
                 if (dc != dnb || (rc = check_dtypes(out, 0, F, dnb, "output")))
@@ -709,8 +757,25 @@ extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* 
     }
     if (he == hipErrorInvalidValue) return gscl_fail(GSCL_ERR_UNSUPPORTED, "no kernel for this kind/dtype/tile");
     if (he != hipSuccess) return gscl_hip_fail(he, "kernel launch");
-    if (red) return finish_reduce(c, fused, fused_result);
+    if (red) return finish_reduce(c, fused, fused_result, fx);
     return GSCL_OK;
+}
+
+extern "C" int gscl_do_all(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* const* in, int n_in,
+                           gscl_grid* const* out, int n_out, const gscl_reduce_desc* fused, double* fused_result) {
+    return do_all_impl(c, op, in, n_in, out, n_out, fused, fused_result, nullptr);
+}
+
+extern "C" int gscl_do_all_noalloc(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* const* in, int n_in,
+                                   gscl_grid* const* out, int n_out, const gscl_reduce_desc* fused,
+                                   double* fused_result) {
+    if (!ctx_ok(c)) return gscl_fail(GSCL_ERR_ARG, "invalid context");
+    if (c->state != CTX_ACTIVE)
+        return gscl_fail(GSCL_ERR_STATE, "do_all outside gscl_begin/gscl_end (context state %d)", c->state);
+    double* base = scratch_of(c->device);
+    if (!base) return gscl_fail(GSCL_ERR_STATE, "fixed scratch of device %d is not set up", c->device);
+    const FixedScratch fx{base, base + GSCL_NOALLOC_PARTIALS};
+    return do_all_impl(c, op, in, n_in, out, n_out, fused, fused_result, &fx);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,6 +71,7 @@ def test_context_state_machine_before_begin():
     arr = (ctypes.c_void_p * 1)(None)
     # iteration spaces outside begin/end are an error (the paper aborts; we return)
     assert L.gscl_do_all(h, ctypes.byref(sd), arr, 1, arr, 1, None, None) == G.ERR_STATE
+    assert L.gscl_do_all_noalloc(h, ctypes.byref(sd), arr, 1, arr, 1, None, None) == G.ERR_STATE
     rd = G.ReduceDesc()
     res = ctypes.c_double()
     assert L.gscl_do_reduce(h, ctypes.byref(rd), None, None, ctypes.byref(res)) == G.ERR_STATE
