@@ -87,7 +87,7 @@ def sync():
 class VarCoef:
     key = "varcoef7_256_f32"
     bytes_per_point = 48  # read u, c0..c6, s (9 x 4 B), write u', r, |F| (3 x 4 B)
-    event_stride = 10     # time every 10th plain sweep launch (90 per 10-step run)
+    event_stride = 1      # one window per run of 9 plain sweeps between fused reductions
 
     def __init__(self, ctx, n=256, sweeps=100, every=10):
         import torch
@@ -113,16 +113,21 @@ class VarCoef:
     def step(self, ev=None):
         G = self.G
         ping = (self.gu, self.gu2)
+        run = 0  # plain sweeps in the open event window
         for k in range(1, self.sweeps + 1):
             src, dst = ping[(k - 1) % 2], ping[k % 2]
             red = k % self.every == 0
-            if ev is not None and not red:
+            if ev is not None and not red and run == 0:
                 ev.begin()
             self.ctx.do_all(G.K_VARCOEF7, [src] + self.gc + [self.gs], [dst, self.gr, self.gf],
                             reduce=(G.R_L2, G.RV_RESIDUAL) if red else None,
                             dev_result=self.norms[k // self.every - 1] if red else None)
-            if ev is not None and not red:
-                ev.end()
+            if not red:
+                run += 1
+            # close the window after the last plain sweep before a fused one
+            if ev is not None and run and ((k + 1) % self.every == 0 or k == self.sweeps):
+                ev.end(run)
+                run = 0
 
     def config(self):
         return {"workload": f"multi-grid variable-coefficient 7-point sweep, {self.n}^3 FP32, "
@@ -716,8 +721,9 @@ class Reduce:
 
 class VC13:
     """Fourth-order 13-point operator on 5 fields sharing 10 coefficient grids,
-    512^3: one apply per storage dtype (BF16, FP16, FP32; FP32 math), and an
-    FP64-residual iterative-refinement solve to 1e-10 in BF16 storage."""
+    512^3.  The timed step is the BF16 apply; after it, per storage dtype
+    (BF16, FP16, FP32; FP32 math): apply GB/s, the apply's error against the
+    oracle, and an FP64-residual iterative-refinement solve to 1e-10."""
     key = "vc13_512"
     bytes_per_point = 40  # BF16: 5 fields + 10 coefficients read, 5 outputs written, 2 B each
 
@@ -745,35 +751,69 @@ class VC13:
             ev.end()
 
     def after(self):
-        """Other storage types and the refinement solve (reported beside the value)."""
+        """Per storage dtype (BF16, FP16, FP32; FP32 math): apply time and GB/s,
+        the apply's error against the oracle on a sampled field, and the
+        FP64-residual refinement solve to 1e-10 with the oracle's recomputed
+        FP64 residual of the answer."""
+        import numpy as np
         import torch
+        import oracle
         G, W, n = self.G, self.W, self.n
         shp = (n, n, n)
         out = {}
-        for dt, name, es in ((G.F16, "f16", 2), (G.F32, "f32", 4)):
-            gc = [self.ctx.grid(shp, dt, halo=0, data=x) for x in self.c]
-            gf = [self.ctx.grid(shp, dt, halo=2, data=x) for x in self.fields]
-            go = [self.ctx.grid(shp, dt, halo=0) for _ in range(5)]
-            fn = lambda: self.ctx.do_all(G.K_VC13_APPLY, gf + gc, go, p=(W.VC13_KAPPA, 0, 5))
+        kappa = W.VC13_KAPPA
+        bn2 = sum(oracle.sumsq(x) for x in self.b)
+        for dt, name, es, prec in ((G.BF16, "bf16", 2, G.PREC_BF16_IR), (G.F16, "f16", 2, G.PREC_F16_IR),
+                                   (G.F32, "f32", 4, G.PREC_F32_IR)):
+            rec = {}
+            if dt == G.BF16:
+                gc, gf, go = self.gc, self.gf, self.go
+            else:
+                gc = [self.ctx.grid(shp, dt, halo=0, data=x) for x in self.c]
+                gf = [self.ctx.grid(shp, dt, halo=2, data=x) for x in self.fields]
+                go = [self.ctx.grid(shp, dt, halo=0) for _ in range(5)]
+            fn = lambda: self.ctx.do_all(G.K_VC13_APPLY, gf + gc, go, p=(kappa, 0, 5))
             fn()
             sync()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
+            ev = KernelEvents(self.ctx.stream)
+            ev.begin()
             for _ in range(5):
                 fn()
-            b.record()
+            ev.end(5)
             sync()
-            ms = a.elapsed_time(b) / 5
-            out[f"apply_{name}"] = {"ms": round(ms, 3), "Gpts_s": round(n ** 3 / ms / 1e6, 2),
-                                    "GBs": round(20 * es * n ** 3 / ms / 1e6, 1)}
-            del gc, gf, go
+            ms, _ = ev.mean_ms()
+            rec["apply_ms"] = round(ms, 4)
+            rec["apply_Gpts_s"] = round(n ** 3 / ms / 1e6, 2)
+            rec["apply_GBs"] = round(20 * es * n ** 3 / ms / 1e6, 1)
+            rec["apply_frac_of_peak"] = round(20 * es * n ** 3 / ms / 1e6 / HBM_PEAK_GBS, 4)
+            # error of the apply against the oracle on field 0 (stored values in FP64)
+            stored = gf[0].numpy().astype(np.float64)
+            ex = oracle.vc13_apply(stored, self.c, kappa)
+            got = go[0].numpy().astype(np.float64)
+            rec["apply_max_rel_err_field0"] = float("%.3e" % (np.abs(got - ex).max() / np.abs(ex).max()))
+            del stored, ex, got
+            if dt != G.BF16:
+                del gf, go
             torch.cuda.empty_cache()
-        gx = [self.ctx.grid(shp, G.F64, halo=2).fill(0.0) for _ in range(5)]
-        gb = [self.ctx.grid(shp, G.F64, halo=0, data=x) for x in self.b]
-        st = self.ctx.solve(G.K_VC13_APPLY, gx, gb, self.gc, kappa=W.VC13_KAPPA, rtol=1e-10, check_every=8,
-                            precision=G.PREC_BF16_IR, inner_sweeps=16)
-        out["refinement_bf16_to_1e-10"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in st.items()}
-        self.extra = out
+            # refinement to 1e-10 with corrections stored in this dtype
+            gx = [self.ctx.grid(shp, G.F64, halo=2).fill(0.0) for _ in range(5)]
+            gb = [self.ctx.grid(shp, G.F64, halo=0, data=x) for x in self.b]
+            st = self.ctx.solve(G.K_VC13_APPLY, gx, gb, gc, kappa=kappa, rtol=1e-10, check_every=8,
+                                precision=prec, inner_sweeps=16)
+            rec["ir_seconds"] = round(st["seconds"], 4)
+            rec["ir_outer"] = st["outer"]
+            rec["ir_inner_sweeps"] = st["sweeps"]
+            rec["ir_rel_residual_device"] = "%.3e" % st["rel_residual"]
+            rn2 = 0.0
+            for f in range(5):
+                rn2 += oracle.sumsq(oracle.vc13_residual(gx[f].numpy(), self.b[f], self.c, kappa))
+            rec["ir_rel_residual_oracle"] = "%.3e" % math.sqrt(rn2 / bn2)
+            del gx, gb
+            if dt != G.BF16:
+                del gc
+            torch.cuda.empty_cache()
+            out[name] = rec
+        self.extra = {"per_dtype": out}
 
     def config(self):
         return {"workload": f"13-point 4th-order operator, 5 fields + 10 coefficient grids, {self.n}^3, "
@@ -803,9 +843,13 @@ WORKLOADS = {"varcoef": VarCoef, "jacobi": Jacobi, "jacobi_tb": JacobiTB, "rbgs"
 
 class KernelEvents:
     """HIP events bracketing launches of the dominant kernel, on the stream the
-    library launches on (the context's stream): every `stride`-th launch, so
-    that on steps of many short launches the events themselves (each pair
-    delays the stream by a few microseconds) do not slow the timed step."""
+    library launches on (the context's stream).  A window holds one launch or
+    a run of back-to-back launches of that kernel (end(n) closes a window of
+    n launches); the mean per launch is the windows' total time over their
+    launch count, so the event pairs (each delays the stream by a few
+    microseconds) are amortized over the run and the per-launch time summed
+    over a step's launches cannot exceed the step.  With `stride` > 1 only
+    every stride-th window is timed."""
 
     def __init__(self, stream, stride=1):
         self.stream = stream
@@ -824,17 +868,26 @@ class KernelEvents:
         e.record(self.stream)
         self._open = e
 
-    def end(self):
+    def end(self, n=1):
         import torch
         if self._open is None:
             return
         e = torch.cuda.Event(enable_timing=True)
         e.record(self.stream)
-        self.pairs.append((self._open, e))
+        self.pairs.append((self._open, e, n))
+        self._open = None
+
+    def describe(self):
+        sizes = sorted({k for _, _, k in self.pairs})
+        what = "one launch" if sizes == [1] else f"runs of {'/'.join(map(str, sizes))} back-to-back launches"
+        every = "every window" if self.stride == 1 else f"1 of every {self.stride} windows"
+        return f"HIP event pairs around {what} of the kernel, {every} of the timed steps"
 
     def mean_ms(self):
-        ts = [a.elapsed_time(b) for a, b in self.pairs]
-        return sum(ts) / len(ts) if ts else float("nan"), len(ts)
+        """(mean milliseconds per launch, launches timed)."""
+        t = sum(a.elapsed_time(b) for a, b, _ in self.pairs)
+        n = sum(k for _, _, k in self.pairs)
+        return t / n if n else float("nan"), n
 
 
 def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=10):
@@ -977,7 +1030,7 @@ def main():
             "traffic": traffic,
             "kernel_ms": round(kmean_ms, 5),
             "launches_timed": nk,
-            "launch_sampling": f"HIP events around 1 of every {ev.stride} launches of the kernel",
+            "launch_sampling": ev.describe(),
             "alg_bytes_per_launch": per_launch_bytes,
             "copy_gbs_same_gpu": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),

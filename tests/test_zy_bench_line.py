@@ -35,6 +35,8 @@ def test_default_bench_line(tmp_path):
     assert abs(rf["achieved"] - rf["alg_bytes_per_launch"] / (rf["kernel_ms"] * 1e-3) / 1e9) <= 0.01 * rf["achieved"]
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
     assert 0 < rf["frac"] < 1.0 and rf["launches_timed"] > 0
+    # the per-launch time over the step's 100 launches fits inside the step
+    assert rf["kernel_ms"] * 100 <= d["ms_per_step"] * 1.01
     assert rf["traffic"] is None or rf["traffic"] > 0
     assert rf["copy_gbs_same_gpu"] > 0
     assert abs(rf["frac_of_copy"] - rf["achieved"] / rf["copy_gbs_same_gpu"]) < 1e-3
