@@ -133,6 +133,15 @@ typedef struct gscl_batch gscl_batch;
  * GSCL_K_VC13_RESID: in = {x_0..x_{F-1} (F64), b_0..b_{F-1} (F64), c0..c9
  *   (any float storage)}, out = {r_f} (F32): r = b - A x in F64, stored F32.
  *   Fused operands: RESIDUAL (r in F64).
+ * GSCL_K_VC13_JACOBI0 (the first GSCL_K_VC13_JACOBI sweep of a correction
+ *   that starts at zero, fused with scaling the right-hand side into its
+ *   storage type): in = {r_0..r_{F-1} (F32), c0..c9}, out = {g_0..g_{F-1},
+ *   d_0..d_{F-1}} with g = s(p[3] r) and d = s(omega g / D), D the diagonal
+ *   of A; coefficients, g and d share one storage s (F32, F16 or BF16).
+ *   p[0] = kappa, p[1] = omega, p[2] = F (1 or 5), p[3] = scale.  d equals a
+ *   GSCL_K_VC13_JACOBI sweep of a zero d with right-hand side g bit for bit.
+ *   Pointwise (no halo read); outputs may not overlap inputs; no fused
+ *   reduction.
  * GSCL_K_POISSON_RESID: in = {x (F64), f (F64)}, out = {r (F32)}:
  *   r = f - (S - 6 x)/h^2 computed in F64, stored F32 (ndim 3); p[1] = h^2.
  *   Fused operand RESIDUAL = r (F64).
@@ -198,7 +207,8 @@ enum {
     GSCL_K_TRIDIAG_BACK = 12,
     GSCL_K_DIAMOND_RECUR = 13,
     GSCL_K_GS2D = 14,
-    GSCL_K_RBGS_TB = 15
+    GSCL_K_RBGS_TB = 15,
+    GSCL_K_VC13_JACOBI0 = 16
 };
 
 typedef struct {
@@ -427,6 +437,20 @@ int gscl_batch_create(gscl_ctx *ctx, const gscl_batch_desc *bd, gscl_batch **out
 /* Device bytes one request of extents n needs inside the batch (its
  * footprint), including the caller's u and f. */
 size_t gscl_batch_footprint(const gscl_batch *b, const int64_t n[3]);
+/* Tile rule of the batched kernels, picked by a tuner (the autotuning the
+ * paper names as future work, Sections 2 and 6): rule i applies to requests
+ * whose largest extent is <= edge[i] (the first such i; edges increasing):
+ * one-sweep tiles of cz[i] z planes (the residual and plain sweep passes) and
+ * blocked-pass tiles of at least tb_cz[i] planes; 0 keeps the built-in
+ * choice, and larger requests use the built-in rule.  Applies to requests
+ * admitted after the call (nrules 0 clears the rule).  A request's tiles
+ * depend only on its own extents and the rule, so its result is the same
+ * alone and among any others under one rule; the blocked passes of
+ * refinement batches carry no reduction, so their tb_cz changes no result.
+ * GSCL_ERR_ARG for more than 64 rules, edges not increasing or chunks
+ * outside 0..1024. */
+int gscl_batch_tile_rule(gscl_batch *b, int nrules, const int32_t *edge, const int32_t *cz,
+                         const int32_t *tb_cz);
 /* Admit a problem: u (initial guess, answer on completion) and f, both F64
  * ndim 3, h2 its spacing squared.  The library allocates the slot's private
  * work grids from the device.  Returns GSCL_ERR_NOMEM when no slot is free or

@@ -27,7 +27,7 @@ F64, F32, F16, BF16, U8, I16, U32 = range(7)
 DIRICHLET, PERIODIC, CLAMP = 0, 1, 2
 K_LINEAR, K_WJACOBI, K_VARCOEF7, K_IMG_BOX5_LAP, K_VC13_APPLY, K_VC13_JACOBI, K_VC13_RESID, \
     K_POISSON_RESID, K_WJACOBI_TB, K_RBGS, K_LINE_RECUR, K_TRIDIAG_FWD, K_TRIDIAG_BACK, \
-    K_DIAMOND_RECUR, K_GS2D, K_RBGS_TB = range(16)
+    K_DIAMOND_RECUR, K_GS2D, K_RBGS_TB, K_VC13_JACOBI0 = range(17)
 R_SUM, R_SUMSQ, R_L2, R_MAXABS, R_ALL_LE = range(5)
 RV_OUT0, RV_UPDATE, RV_RESIDUAL = range(3)
 PREC_F64, PREC_F32_IR, PREC_BF16_IR, PREC_F16_IR = range(4)
@@ -110,6 +110,8 @@ _SIGS = {
                                   _vp, ctypes.c_size_t, _P(SolveStats)]),
     "gscl_batch_create": (ctypes.c_int, [_vp, _P(BatchDesc), _P(_vp)]),
     "gscl_batch_footprint": (ctypes.c_size_t, [_vp, _P(_i64)]),
+    "gscl_batch_tile_rule": (ctypes.c_int, [_vp, ctypes.c_int, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                            _P(ctypes.c_int32)]),
     "gscl_batch_admit": (ctypes.c_int, [_vp, _vp, _vp, _f64, _P(ctypes.c_int)]),
     "gscl_batch_step": (ctypes.c_int, [_vp]),
     "gscl_batch_poll": (ctypes.c_int, [_vp, _P(ctypes.c_int), ctypes.c_int, _P(ctypes.c_int)]),
@@ -498,10 +500,19 @@ class Batch:
         self.handle = h
         self.max_slots = max_slots
         self.sweeps_per_step = sweeps_per_step
+        self.tile_rule = []
 
     def footprint(self, shape) -> int:
         n = (_i64 * 3)(shape[2], shape[1], shape[0])
         return int(lib().gscl_batch_footprint(self.handle, n))
+
+    def set_tile_rule(self, rules: Sequence[tuple]):
+        """rules = [(edge, cz, tb_cz), ...] with increasing edges (see
+        gscl_batch_tile_rule); applies to requests admitted afterwards."""
+        n = len(rules)
+        arr = [(ctypes.c_int32 * max(n, 1))(*[int(r[k]) for r in rules]) for k in range(3)]
+        check(lib().gscl_batch_tile_rule(self.handle, n, arr[0], arr[1], arr[2]), "gscl_batch_tile_rule")
+        self.tile_rule = [tuple(int(v) for v in r) for r in rules]
 
     def admit(self, u: Grid, f: Grid, h2: float) -> int | None:
         """Slot id, or None when no slot / budget is free (the caller queues)."""

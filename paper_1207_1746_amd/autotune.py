@@ -8,6 +8,11 @@ HIP events, keeps the fastest, installs it in the context with
 (gfx arch, kind, dtype, extents).  Outputs do not depend on the tile shape
 (only the fused-reduction rounding order does), so tuning never changes a
 do_all result.
+
+For the batched executor it picks, per request-size bucket, the z chunks of
+the one-sweep and blocked-pass tiles (``gscl_batch_tile_rule``) by timing
+steps of a batch filled with requests of the bucket's size, and caches the
+rule under (gfx arch, precision, method, step and pass lengths, bucket).
 """
 from __future__ import annotations
 
@@ -25,6 +30,10 @@ RADIUS2 = (G.K_VC13_APPLY, G.K_VC13_JACOBI, G.K_VC13_RESID)
 
 
 BLOCKED = (G.K_WJACOBI_TB, G.K_RBGS_TB)
+
+# request-size buckets of the batched executor: (largest extent, cube side
+# timed for the bucket)
+BATCH_BUCKETS = ((48, 40), (96, 80), (144, 128), (192, 176))
 
 
 def candidates(kind: int, dtype: int, nz: int) -> list[tuple[int, int, int]]:
@@ -122,6 +131,53 @@ class Tuner:
             self.ctx.tile_set(kind, grid, tuple(rec["tile"]))
             return True
         return False
+
+    def tune_batch(self, precision: int = G.PREC_F32_IR, method: int = G.BATCH_JACOBI,
+                   sweeps_per_step: int = 64, sweeps_per_pass: int = 4, buckets=BATCH_BUCKETS,
+                   slots: int = 8, reps: int = 3, force: bool = False) -> list[tuple]:
+        """Tile rule [(edge, cz, tb_cz), ...] for a batch of this
+        configuration: per bucket, the (cz, tb_cz) whose step is fastest on a
+        batch of `slots` requests of the bucket's size (never converging
+        during the timing)."""
+        import numpy as np
+        import torch
+        ctx = self.ctx
+        rules = []
+        for edge, n in buckets:
+            key = f"batch|{self.arch}|p{precision}|m{method}|S{sweeps_per_step}|k{sweeps_per_pass}|{edge}"
+            if not force and key in self.table:
+                rules.append((edge, *self.table[key]["rule"]))
+                continue
+            shape = (n, n, n)
+            f = ctx.grid(shape, G.F64, halo=0, data=np.random.default_rng(n).standard_normal(shape))
+            us = [ctx.grid(shape, G.F64, halo=1) for _ in range(slots)]
+            czs = (4, 8, 16)
+            tbs = (4, 8, 16, 32) if sweeps_per_pass > 1 else (0,)
+            results = []
+            for cz in czs:
+                for tb in tbs:
+                    probe = G.Batch(ctx, max_slots=slots, precision=precision, hbm_budget=1 << 20, method=method,
+                                    sweeps_per_step=sweeps_per_step, sweeps_per_pass=sweeps_per_pass)
+                    budget = int(slots * probe.footprint(shape) * 1.25) + (64 << 20)
+                    probe.close()
+                    b = G.Batch(ctx, max_slots=slots, precision=precision, sweeps_per_step=sweeps_per_step,
+                                rtol=1e-300, hbm_budget=budget, method=method, omega=6 / 7 if method == G.BATCH_JACOBI
+                                else 0.0, sweeps_per_pass=sweeps_per_pass, max_sweeps=10 ** 9)
+                    b.set_tile_rule([(edge, cz, tb)])
+                    for u in us:
+                        u.fill(0.0)
+                        assert b.admit(u, f, 1.0 / (n + 1) ** 2) is not None
+                    ms = time_call(b.step, reps=reps, warmup=1, stream=ctx.stream)
+                    b.close()
+                    results.append((ms, (cz, tb)))
+            del us, f
+            torch.cuda.empty_cache()
+            results.sort()
+            ms, best = results[0]
+            self.table[key] = {"rule": list(best), "ms_per_step": round(ms, 4),
+                               "tried": [[list(t), round(m, 4)] for m, t in results]}
+            rules.append((edge, *best))
+        return rules
 
     def save(self, path: str | None = None):
         path = path or self.cache_path

@@ -61,6 +61,7 @@ struct BSlot {
     int tile_begin, ntiles;
     int tntx, tnty, tncz, tcz;   // blocked-pass tiles (sweeps_per_pass > 1)
     int tb_begin, tb_ntiles;
+    int tb_czmin;                // smallest blocked-pass z chunk of the slot
 };
 
 struct BState {
@@ -345,6 +346,11 @@ struct gscl_batch {
     bool dirty;
     gscl_graph* graph;
     int persist_blocks;
+    // tuned tile rule by slot size (gscl_batch_tile_rule): for slots whose
+    // largest extent is <= rule_edge[i] (first such i), one-sweep tiles of
+    // rule_cz[i] planes and blocked-pass tiles of at least rule_tbcz[i]
+    // planes (0: the built-in choice)
+    std::vector<int> rule_edge, rule_cz, rule_tbcz;
 };
 
 static size_t slot_work_bytes(const gscl_batch_desc& bd, const gscl_grid_desc& d) {
@@ -366,6 +372,23 @@ extern "C" size_t gscl_batch_footprint(const gscl_batch* b, const int64_t n[3]) 
     d.dtype = GSCL_F64;
     if (gscl_grid_layout(&d)) return 0;
     return 2 * gscl_grid_bytes(&d) + slot_work_bytes(b->desc, d);
+}
+
+extern "C" int gscl_batch_tile_rule(gscl_batch* b, int nrules, const int32_t* edge, const int32_t* cz,
+                                    const int32_t* tb_cz) {
+    if (!b || b->magic != BATCH_MAGIC) return gscl_fail(GSCL_ERR_ARG, "invalid batch");
+    if (nrules < 0 || nrules > 64) return gscl_fail(GSCL_ERR_ARG, "nrules must be 0..64");
+    if (nrules > 0 && (!edge || !cz || !tb_cz)) return gscl_fail(GSCL_ERR_ARG, "null rule array");
+    for (int i = 0; i < nrules; ++i) {
+        if (edge[i] < 1 || (i > 0 && edge[i] <= edge[i - 1]))
+            return gscl_fail(GSCL_ERR_ARG, "rule edges must be positive and increasing");
+        if (cz[i] < 0 || cz[i] > 1024 || tb_cz[i] < 0 || tb_cz[i] > 1024)
+            return gscl_fail(GSCL_ERR_ARG, "rule z chunks must be 0..1024");
+    }
+    b->rule_edge.assign(edge, edge + nrules);
+    b->rule_cz.assign(cz, cz + nrules);
+    b->rule_tbcz.assign(tb_cz, tb_cz + nrules);
+    return GSCL_OK;
 }
 
 extern "C" int gscl_batch_create(gscl_ctx* c, const gscl_batch_desc* bd, gscl_batch** out) {
@@ -485,14 +508,18 @@ static int upload_table(gscl_batch* b) {
         // tiling changes no result; when few slots are left (the tail of a
         // stream), shorter chunks spread the remaining work over more CUs:
         // halve the minimum chunk until the batch has 512 blocked tiles.
-        for (int czmin = TB_CZMIN;; czmin /= 2) {
+        for (int shift = 0;; ++shift) {
             int64_t total = 0;
+            bool all_one = true;
             for (int id = 0; id < b->desc.max_slots; ++id)
                 if (b->used[id]) {
-                    set_tb_tiles(b->slot[id], b->desc.sweeps_per_pass, czmin);
-                    total += b->slot[id].tb_ntiles;
+                    BSlot& sl = b->slot[id];
+                    const int czmin = std::max(1, sl.tb_czmin >> shift);
+                    all_one = all_one && czmin == 1;
+                    set_tb_tiles(sl, b->desc.sweeps_per_pass, czmin);
+                    total += sl.tb_ntiles;
                 }
-            if (total >= 512 || czmin == 1) break;
+            if (total >= 512 || all_one) break;
         }
     }
     int n = 0, tiles = 0, tb_tiles = 0;
@@ -590,12 +617,23 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
         s.d2 = (float*)(mem + r4);
         s.rh = (float*)(mem + 2 * r4);
     }
-    s.cz = std::min(8, s.nz);
+    // tiles from the slot's own extents (and the batch's tile rule), so the
+    // slot's results do not depend on the other slots
+    int rcz = 0, rtb = 0;
+    const int ext = std::max(s.nx, std::max(s.ny, s.nz));
+    for (size_t i = 0; i < b->rule_edge.size(); ++i)
+        if (ext <= b->rule_edge[i]) {
+            rcz = b->rule_cz[i];
+            rtb = b->rule_tbcz[i];
+            break;
+        }
+    s.cz = std::min(rcz > 0 ? rcz : 8, s.nz);
     s.ntx = (s.nx + 64 * BV - 1) / (64 * BV);
     s.nty = (s.ny + BNW - 1) / BNW;
     s.ncz = (s.nz + s.cz - 1) / s.cz;
     s.ntiles = s.ntx * s.nty * s.ncz;
-    if (b->desc.sweeps_per_pass > 1) set_tb_tiles(s, b->desc.sweeps_per_pass, TB_CZMIN);
+    s.tb_czmin = rtb > 0 ? rtb : TB_CZMIN;
+    if (b->desc.sweeps_per_pass > 1) set_tb_tiles(s, b->desc.sweeps_per_pass, s.tb_czmin);
     b->slot[id] = s;
     b->used[id] = true;
     b->work_ptr[id] = mem;

@@ -33,6 +33,18 @@ hipError_t launch_vc13_jacobi(TArgs& a, int dtype_nb, int dtype_g, int dtype_c, 
                               const TileCfg& c, bool red, hipStream_t s, int* nblocks);
 hipError_t launch_vc13_resid(TArgs& a, int dtype_c, int nfields, const TileCfg& c, bool red,
                              hipStream_t s, int* nblocks);
+// First Jacobi sweep of a zero correction, fused with scaling the residual
+// into the storage type: g_f = s(r_f * p[3]), d_f = s(omega g_f / D).
+// r F32; coefficients, g and d in storage `dtype` (F32, F16 or BF16).
+struct J0Args {
+    Geo g;
+    const float* r[5];
+    const void* c[10];
+    void* gout[5];
+    void* dout[5];
+    double p[8];  // p[0] = kappa, p[1] = omega, p[3] = scale
+};
+hipError_t launch_vc13_first(J0Args& a, int dtype, int nfields, hipStream_t s);
 // Blocks a tiled launch with this configuration would use.
 int tiled_blocks(const Geo& g, const TileCfg& c);
 

@@ -378,12 +378,27 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
             ++outer;
             // scale into the inner storage range (F16 needs it; others use 1)
             const double sigma = s == GSCL_F16 ? sqrt(res2 / (double)npts) : 1.0;
-            for (int f = 0; f < nf; ++f) {
-                const gk::Geo g = geo_of(x[f]);
-                if (!poisson) GSCL_HIP(gk::launch_axpby(rh[f]->ptr, s, r[f]->ptr, GSCL_F32, 1.0 / sigma, nullptr, 0, 0.0, g, c->stream));
-                GSCL_HIP(gk::launch_fill(d[f]->ptr, s == GSCL_F64 ? GSCL_F64 : (poisson ? GSCL_F32 : s), 0.0, g, c->stream));
+            int k0 = 1;
+            if (poisson) {
+                GSCL_HIP(gk::launch_fill(d[0]->ptr, GSCL_F32, 0.0, geo_of(x[0]), c->stream));
+            } else {
+                // the first sweep of d = 0 is pointwise: fused with scaling
+                // r into the storage type (rh), it writes d2 as sweep 1 would
+                gscl_stencil_desc fop;
+                memset(&fop, 0, sizeof fop);
+                fop.kind = GSCL_K_VC13_JACOBI0;
+                fop.p[0] = sd->kappa;
+                fop.p[1] = sd->omega;
+                fop.p[2] = nf;
+                fop.p[3] = 1.0 / sigma;
+                std::vector<gscl_grid*> fin(r.begin(), r.end()), fout(rh.begin(), rh.end());
+                for (int k2 = 0; k2 < 10; ++k2) fin.push_back(const_cast<gscl_grid*>(coef[k2]));
+                for (int f = 0; f < nf; ++f) fout.push_back(d2[f]);
+                e = gscl_do_all(c, &fop, fin.data(), (int)fin.size(), fout.data(), (int)fout.size(), nullptr, nullptr);
+                if (e) return e;
+                k0 = 2;
             }
-            for (int k = 1; k <= m; ++k) {
+            for (int k = k0; k <= m; ++k) {
                 const bool odd = k % 2 == 1;
                 std::vector<gscl_grid*> iin, iout;
                 gscl_stencil_desc iop;

@@ -71,7 +71,8 @@ class SolveServer:
     def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
                  rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
                  hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7,
-                 pipelined: bool = True, method: int = G.BATCH_JACOBI, sweeps_per_pass: int = 4):
+                 pipelined: bool = True, method: int = G.BATCH_JACOBI, sweeps_per_pass: int = 4,
+                 tile_rule=None):
         self.ctx = ctx
         self.pipelined = pipelined
         # sweeps run as temporally blocked passes of 4 (sweeps or colour
@@ -84,6 +85,8 @@ class SolveServer:
                              rtol=rtol, hbm_budget=hbm_budget, max_sweeps=max_sweeps, method=method,
                              sweeps_per_pass=sweeps_per_pass)
         self.hbm_budget = hbm_budget
+        if tile_rule:
+            self.batch.set_tile_rule(tile_rule)
 
     def _reject(self, job: Job, now: float, why: str):
         job.state = 3
@@ -106,9 +109,10 @@ class SolveServer:
         job.admitted_at = now
         return True
 
-    def run(self, jobs: list[Job], realtime: bool = True) -> ServeReport:
+    def run(self, jobs: list[Job], realtime: bool = True, on_done=None) -> ServeReport:
         """Serve `jobs` (sorted by arrival).  realtime=False admits by arrival
-        order only (closed loop, no waiting for the clock)."""
+        order only (closed loop, no waiting for the clock).  on_done(job), if
+        given, is called as each request completes."""
         pending = sorted(jobs, key=lambda j: j.arrival)
         queue: list[Job] = []
         running: dict[int, Job] = {}
@@ -153,6 +157,8 @@ class SolveServer:
                 st = self.batch.retire(slot)
                 job.done_at = time.perf_counter() - t0
                 job.sweeps, job.rel_residual, job.state = st["sweeps"], st["rel_residual"], st["state"]
+                if on_done:
+                    on_done(job)
         return ServeReport(jobs, time.perf_counter() - t0, steps, max_running, occ)
 
     def close(self):
@@ -161,9 +167,10 @@ class SolveServer:
 
 def serve_sequential(ctx: G.Context, jobs: list[Job], rtol: float = 1e-8, omega: float = 6 / 7,
                      check_every: int = 64, precision: int = G.PREC_F64, inner_sweeps: int = 64,
-                     realtime: bool = True, kind: int = G.K_WJACOBI) -> ServeReport:
+                     realtime: bool = True, kind: int = G.K_WJACOBI, on_done=None) -> ServeReport:
     """One solve at a time with gscl_solve (the plain path), same queueing rules.
-    kind K_WJACOBI or K_RBGS (red-black SOR, omega = 0 for the optimal weight)."""
+    kind K_WJACOBI or K_RBGS (red-black SOR, omega = 0 for the optimal weight).
+    on_done(job), if given, is called as each request completes."""
     t0 = time.perf_counter()
     for job in sorted(jobs, key=lambda j: j.arrival):
         now = time.perf_counter() - t0
@@ -178,4 +185,6 @@ def serve_sequential(ctx: G.Context, jobs: list[Job], rtol: float = 1e-8, omega:
                        check_every=check_every, precision=precision, inner_sweeps=inner_sweeps)
         job.done_at = time.perf_counter() - t0
         job.sweeps, job.rel_residual, job.state = st["sweeps"], st["rel_residual"], 2
+        if on_done:
+            on_done(job)
     return ServeReport(jobs, time.perf_counter() - t0, 0, 1, [1])

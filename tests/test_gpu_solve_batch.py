@@ -115,10 +115,12 @@ def test_vc13_solve_per_precision(ctx, prec, dt):
 
 
 def _batch_solve(ctx, reqs, prec, S, admit_at=None, use_graph=True, rtol=1e-8, method=G.BATCH_JACOBI,
-                 omega=6 / 7, sweeps_per_pass=1, hbm_budget=1 << 30):
+                 omega=6 / 7, sweeps_per_pass=1, hbm_budget=1 << 30, rule=None):
     """Run requests through one batch; admit_at[i] = step index to admit request i."""
     b = G.Batch(ctx, max_slots=8, precision=prec, sweeps_per_step=S, use_graph=use_graph, rtol=rtol,
                 hbm_budget=hbm_budget, method=method, omega=omega, sweeps_per_pass=sweeps_per_pass)
+    if rule:
+        b.set_tile_rule(rule)
     admit_at = admit_at or [0] * len(reqs)
     grids = {}
     out = {}
@@ -260,6 +262,57 @@ def test_batch_f32_refinement_large_slots_1e10(ctx):
                                  hbm_budget=4 << 30)[0]
             assert np.array_equal(alone[0], mix[i][0]), r.n
             assert alone[1]["sweeps"] == mix[i][1]["sweeps"], r.n
+
+
+def test_batch_tile_rule(ctx):
+    """Tuned tile rules of the batched kernels.  Refinement with blocked
+    passes: a rule that changes only the blocked-pass chunks gives the untuned
+    answers bit for bit (those passes carry no reduction).  A rule that
+    changes the one-sweep chunks (which fold the residual) keeps every answer
+    the same alone and in the mix, and within rtol by the oracle."""
+    reqs = [_req(n, seed=n + 11, rid=i) for i, n in enumerate((17, 37, 45, 24, 9))]
+    at = [0, 0, 2, 3, 1]
+    base = _batch_solve(ctx, reqs, G.PREC_F32_IR, 16, admit_at=at, sweeps_per_pass=4)
+    tb_only = _batch_solve(ctx, reqs, G.PREC_F32_IR, 16, admit_at=at, sweeps_per_pass=4,
+                           rule=[(24, 0, 2), (40, 0, 32), (64, 0, 1)])
+    for i in range(len(reqs)):
+        assert np.array_equal(base[i][0], tb_only[i][0]) and base[i][1]["sweeps"] == tb_only[i][1]["sweeps"], i
+    rule = [(20, 2, 0), (40, 16, 0), (64, 4, 8)]
+    for prec, k in ((G.PREC_F64, 1), (G.PREC_F32_IR, 4)):
+        mix = _batch_solve(ctx, reqs, prec, 16, admit_at=at, sweeps_per_pass=k, rule=rule)
+        for i, r in enumerate(reqs):
+            assert mix[i][1]["state"] == 2
+            alone = _batch_solve(ctx, [r], prec, 16, sweeps_per_pass=k, rule=rule, use_graph=False)[0]
+            assert np.array_equal(alone[0], mix[i][0]) and alone[1]["sweeps"] == mix[i][1]["sweeps"], (prec, i)
+            _, f = W.poisson_fields(r)
+            assert _oracle_rel_residual(mix[i][0], f, r.h2) <= 1e-8 * 1.01
+    b = G.Batch(ctx, max_slots=2)
+    for bad in ([(40, 4, 4), (20, 4, 4)], [(0, 4, 4)], [(40, -1, 4)], [(40, 4, 2000)]):
+        with pytest.raises(G.GsclError) as e:
+            b.set_tile_rule(bad)
+        assert e.value.code == G.ERR_ARG
+    b.set_tile_rule([])
+    b.close()
+
+
+def test_autotuner_batch_rule(ctx, tmp_path):
+    """The tuner times candidate chunks per request-size bucket on a filled
+    batch, returns a rule the executor accepts, and caches it."""
+    from paper_1207_1746_amd import autotune
+    path = str(tmp_path / "tiles.json")
+    t = autotune.Tuner(ctx, cache_path=path)
+    rule = t.tune_batch(buckets=((24, 20), (40, 36)), slots=3, reps=1, sweeps_per_step=16)
+    assert [r[0] for r in rule] == [24, 40]
+    assert all(r[1] in (4, 8, 16) and r[2] in (4, 8, 16, 32) for r in rule)
+    t.save()
+    again = autotune.Tuner(ctx, cache_path=path).tune_batch(buckets=((24, 20), (40, 36)), slots=3, reps=1,
+                                                           sweeps_per_step=16)
+    assert again == rule
+    reqs = [_req(n, seed=n + 13, rid=i) for i, n in enumerate((21, 33))]
+    res = _batch_solve(ctx, reqs, G.PREC_F32_IR, 16, sweeps_per_pass=4, rule=rule)
+    for i, r in enumerate(reqs):
+        _, f = W.poisson_fields(r)
+        assert res[i][1]["state"] == 2 and _oracle_rel_residual(res[i][0], f, r.h2) <= 1e-8 * 1.01
 
 
 @pytest.mark.parametrize("k,S", [(4, 4), (2, 6)])

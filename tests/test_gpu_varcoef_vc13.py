@@ -182,3 +182,63 @@ def test_vc13_five_field_tiling_invariance(ctx, dt, bc):
                 terms = 1.5 * max(np.abs(stored).max(), bcv) * (1 + W.VC13_KAPPA * 3 * (4 / 3 * 2 * 2 + 4 / 12))
                 tol = 4 * us * max(np.abs(ex).max(), 1.0) + 64 * (U32 if dt != G.F64 else 1e-16) * terms
                 assert np.abs(ref[f] - ex).max() <= tol, f
+
+
+def _bits(grid):
+    import torch
+    v = grid.view.contiguous()
+    return v.view(torch.int16 if v.element_size() == 2 else torch.int32).cpu().numpy()
+
+
+@pytest.mark.parametrize("dt", [G.BF16, G.F16, G.F32])
+@pytest.mark.parametrize("nf,scale", [(5, 1.0), (5, 0.37), (1, 3.0)])
+def test_vc13_jacobi0_equals_sweep_of_zero(ctx, dt, nf, scale):
+    """The fused first sweep of a zero correction: g is the scaled residual
+    rounded to the storage type (as the host rounds FP64 -> FP32 -> storage),
+    and d equals a VC13_JACOBI sweep of a zero d with right-hand side g bit
+    for bit (ragged row: nx = 70)."""
+    import torch
+    shape = (9, 13, 70)
+    c, _ = W.vc13_grids(shape[2], shape[1], shape[0], nf)
+    rng = np.random.default_rng(11)
+    r = [rng.standard_normal(shape).astype(np.float32) for _ in range(nf)]
+    gr = [ctx.grid(shape, G.F32, halo=0, data=x) for x in r]
+    gc = [ctx.grid(shape, dt, halo=0, data=x) for x in c]
+    gg = [ctx.grid(shape, dt, halo=0) for _ in range(nf)]
+    gd = [ctx.grid(shape, dt, halo=0) for _ in range(nf)]
+    omega = 6 / 7
+    ctx.do_all(G.K_VC13_JACOBI0, gr + gc, gg + gd, p=(W.VC13_KAPPA, omega, nf, scale))
+    tdt = {G.BF16: torch.bfloat16, G.F16: torch.float16, G.F32: torch.float32}[dt]
+    for f in range(nf):
+        host = torch.from_numpy((scale * r[f].astype(np.float64)).astype(np.float32)).to(tdt)
+        assert torch.equal(gg[f].view.cpu(), host), f
+    z = [ctx.grid(shape, dt, halo=2).fill(0.0) for _ in range(nf)]
+    o = [ctx.grid(shape, dt, halo=0) for _ in range(nf)]
+    ctx.do_all(G.K_VC13_JACOBI, z + gg + gc, o, p=(W.VC13_KAPPA, omega, nf))
+    for f in range(nf):
+        assert np.array_equal(_bits(gd[f]), _bits(o[f])), f
+    # d = omega g / D against the oracle's diagonal: FP32 forms D from ten
+    # rounded terms, omega / D and the product (<= 16 roundings of 2^-24),
+    # then d is rounded once to the storage type
+    D = oracle.vc13_diag(c, W.VC13_KAPPA)
+    us = {G.F32: U32, G.F16: 2.0 ** -11, G.BF16: 2.0 ** -8}[dt]
+    for f in range(nf):
+        g64 = gg[f].view.double().cpu().numpy()
+        ex = omega * g64 / D
+        assert np.abs(gd[f].view.double().cpu().numpy() - ex).max() <= (us + 16 * U32) * np.abs(ex).max()
+
+
+def test_vc13_jacobi0_errors(ctx):
+    shape = (4, 5, 6)
+    c, _ = W.vc13_grids(6, 5, 4, 1)
+    gr = [ctx.grid(shape, G.F32, halo=0)]
+    gc = [ctx.grid(shape, G.BF16, halo=0, data=x) for x in c]
+    gg = ctx.grid(shape, G.BF16, halo=0)
+    gd = ctx.grid(shape, G.BF16, halo=0)
+    p = (W.VC13_KAPPA, 6 / 7, 1, 1.0)
+    for ins, outs, code in ((gr + gc, [gg], G.ERR_ARG),                   # one output missing
+                            (gc[:1] + gc, [gg, gd], G.ERR_DTYPE),          # residual not F32
+                            (gr + gc, [gg, gc[0]], G.ERR_ALIAS)):          # output is an input
+        with pytest.raises(G.GsclError) as e:
+            ctx.do_all(G.K_VC13_JACOBI0, ins, outs, p=p)
+        assert e.value.code == code
