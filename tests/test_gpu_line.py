@@ -72,8 +72,9 @@ def test_thomas_matches_oracle(ctx, axis, direction):
 @pytest.mark.parametrize("direction", [1, -1])
 @pytest.mark.parametrize("dt", [G.F64, G.F32])
 def test_lines_along_x_several_blocks(ctx, direction, dt):
-    """Lines along x run 256 to a block in chunks of 8 or 16 cells: 350 lines
-    (one full block and a partial one) of 203 cells (a ragged last chunk in
+    """Lines along x run 128 to a block (256 for the FP32 recurrence and
+    substitution) in chunks of 32 cells: 350 lines (full blocks and a partial
+    one) of 203 cells (six whole chunks and a ragged last one of 11 cells, in
     either order), recurrence and both Thomas passes against the oracle."""
     shape = (5, 70, 203)
     g = np.random.default_rng(46)
