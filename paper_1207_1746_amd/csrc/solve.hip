@@ -144,7 +144,10 @@ extern "C" int gscl_solve(gscl_ctx* c, const gscl_solve_desc* sd, gscl_grid* con
         if (x[f]->d.bc != GSCL_BC_DIRICHLET || x[f]->d.bc_value != 0.0)
             return gscl_fail(GSCL_ERR_ARG, "solve uses a zero Dirichlet boundary");
     }
-    if (x[0]->d.pitch[0] % 16) return gscl_fail(GSCL_ERR_SHAPE, "solve needs row pitches that are a multiple of 16 elements");
+    // the workspace grids (F32, 2-byte) share x's pitches in elements: keep
+    // every row and plane start 16-byte aligned for the narrowest type too
+    if (x[0]->d.pitch[0] % 16 || x[0]->d.pitch[1] % 16)
+        return gscl_fail(GSCL_ERR_SHAPE, "solve needs row and plane pitches that are multiples of 16 elements");
     const size_t need = gscl_solve_workspace_bytes(sd, x[0], nf);
     if (!workspace || ws_bytes < need)
         return gscl_fail(GSCL_ERR_NOMEM, "workspace of %zu bytes needed", need);

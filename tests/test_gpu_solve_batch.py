@@ -91,6 +91,15 @@ def test_poisson_solver_errors(ctx):
     u.fill(1.0)
     st = ctx.solve(G.K_WJACOBI, [u], [z], h2=req.h2, rtol=1e-8, check_every=4)
     assert st["sweeps"] == 0 and np.all(u.numpy() == 0.0)
+    # pitches whose narrow-type workspace rows or planes would not start on
+    # 16-byte boundaries are refused before any launch
+    for pitch in ((18, 18 * 12), (16, 16 * 12 + 2)):
+        d = G.make_desc(f.shape, G.F64, halo=1, pitch=pitch)
+        up = G.Grid(ctx, d).fill(0.0)
+        fp = G.Grid(ctx, G.make_desc(f.shape, G.F64, halo=0, pitch=pitch)).upload(f)
+        with pytest.raises(G.GsclError) as e:
+            ctx.solve(G.K_WJACOBI, [up], [fp], h2=req.h2, rtol=1e-8, check_every=4, precision=G.PREC_F32_IR)
+        assert e.value.code == G.ERR_SHAPE, pitch
 
 
 @pytest.mark.parametrize("prec,dt", [(G.PREC_F64, G.BF16), (G.PREC_F32_IR, G.F32),
