@@ -381,6 +381,12 @@ static int check_common(gscl_ctx* c, gscl_grid* const* in, int n_in, gscl_grid* 
     return GSCL_OK;
 }
 
+// Temporally blocked kernels address a point as a plane address plus a
+// 32-bit byte offset within the plane.
+static bool tb_plane_fits(const gscl_grid* g, int esize) {
+    return ((g->d.n[1] - 1) * g->d.pitch[0] + g->d.n[0]) * (int64_t)esize <= (int64_t)UINT32_MAX;
+}
+
 static int check_nb(gscl_grid* const* in, int first, int count, int radius, gscl_grid* const* out, int n_out,
                     int ndim_req) {
     for (int i = first; i < first + count; ++i) {
@@ -586,6 +592,8 @@ static int do_all_impl(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* cons
                 return gscl_fail(GSCL_ERR_ALIAS, "WJACOBI_TB output aliases the right-hand side");
             if (g0->d.bc == GSCL_BC_CLAMP)
                 return gscl_fail(GSCL_ERR_UNSUPPORTED, "WJACOBI_TB supports the Dirichlet and periodic rules");
+            if (!tb_plane_fits(g0, dt == GSCL_F64 ? 8 : 4))
+                return gscl_fail(GSCL_ERR_SHAPE, "WJACOBI_TB needs planes under 4 GiB");
             if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "WJACOBI_TB needs h^2 != 0 in p[1]");
             const double kd = op->p[2];
             if (!(kd >= 1.0 && kd <= (double)gk::TB_KMAX) || kd != (double)(int)kd)
@@ -618,6 +626,8 @@ static int do_all_impl(gscl_ctx* c, const gscl_stencil_desc* op, gscl_grid* cons
             if (n_in == 2 && overlaps(in[1], out[0]))
                 return gscl_fail(GSCL_ERR_ALIAS, "RBGS_TB output aliases the right-hand side");
             if (g0->d.bc != GSCL_BC_DIRICHLET) return gscl_fail(GSCL_ERR_UNSUPPORTED, "RBGS_TB uses the Dirichlet rule");
+            if (!tb_plane_fits(g0, dt == GSCL_F64 ? 8 : 4))
+                return gscl_fail(GSCL_ERR_SHAPE, "RBGS_TB needs planes under 4 GiB");
             if (op->p[1] == 0.0) return gscl_fail(GSCL_ERR_ARG, "RBGS_TB needs h^2 != 0 in p[1]");
             if (op->p[2] != 0.0 && op->p[2] != 1.0) return gscl_fail(GSCL_ERR_ARG, "RBGS_TB first colour p[2] must be 0 or 1");
             const double kd = op->p[3];

@@ -159,11 +159,14 @@ __global__ __launch_bounds__(64 * BNW) void batch_sweep(const BSlot* __restrict_
 // F32 residual as right-hand side; MODE_RBGS_TB: k red-black colour passes
 // (red first) with the slot's weight, u -> u2 or back.  RED: the residual of
 // the last sweep's input, per blocked tile, into the partials.
-template <int MODE, bool RED>
-__global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restrict__ slots, const BState* st,
-                                                           const BHeader* hdr, double* partials, int parity,
-                                                           double omega, int k) {
-    using T = typename std::conditional<MODE == MODE_F32, float, double>::type;
+template <int MODE>
+using BatchT = typename std::conditional<MODE == MODE_F32, float, double>::type;
+
+template <int MODE, bool RED, int K>
+__global__ __launch_bounds__(64 * gk::TB_NW, (gk::tb_waves_per_eu<BatchT<MODE>, K, RED, MODE == MODE_RBGS_TB>()))
+void batch_tb(const BSlot* __restrict__ slots, const BState* st, const BHeader* hdr, double* partials, int parity,
+              double omega) {
+    using T = BatchT<MODE>;
     const int n = hdr->nslots, total = hdr->total_tb_tiles;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int si = find_slot<true>(slots, n, t);
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restri
         a.p[1] = s.h2;
         a.p[2] = s.ih2;
         a.p[3] = 0.0;  // red-black: the first colour
-        a.k = k;
+        a.k = K;
         a.ntx = s.tntx;
         a.nty = s.tnty;
         a.ncz = s.tncz;
@@ -201,7 +204,11 @@ __global__ __launch_bounds__(64 * gk::TB_NW) void batch_tb(const BSlot* __restri
             a.f = s.f;
         }
         double acc = 0.0;
-        gk::tb7_tile<T, true, gk::TB_KMAX, RED, MODE == MODE_RBGS_TB>(a, t - s.tb_begin, acc);
+        // (the FP32 four-level pass keeps one step per group: with the slot
+        // bookkeeping, two would spill)
+        constexpr bool RB = MODE == MODE_RBGS_TB;
+        constexpr int U = MODE == MODE_F32 && K == 4 ? 1 : gk::tb_unroll<T, K, RED, RB>();
+        gk::tb7_tile<T, true, K, RED, RB, U>(a, t - s.tb_begin, acc);
         if (RED) gk::block_reduce(acc, a.ra, t);
     }
 }
@@ -572,6 +579,10 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     if (u->d.halo < 1) return gscl_fail(GSCL_ERR_HALO, "u must declare halo >= 1");
     if (!(h2 > 0)) return gscl_fail(GSCL_ERR_ARG, "h2 must be positive");
     if (u->d.n[0] * u->d.n[1] * u->d.n[2] == 0) return gscl_fail(GSCL_ERR_SHAPE, "empty grid");
+    // blocked passes address a point as a plane address plus a 32-bit byte
+    // offset within the plane
+    if (b->desc.sweeps_per_pass > 1 && ((u->d.n[1] - 1) * u->d.pitch[0] + u->d.n[0]) * 8 > (int64_t)UINT32_MAX)
+        return gscl_fail(GSCL_ERR_SHAPE, "blocked passes need planes under 4 GiB");
     int id = -1;
     for (int i = 0; i < b->desc.max_slots; ++i)
         if (!b->used[i]) {
@@ -657,6 +668,24 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     return GSCL_OK;
 }
 
+// One blocked pass of kp levels: 2..TB_KMAX (red-black passes validate to 2
+// or 4, so that mode has no 3-level kernel).
+template <int MODE, bool RED>
+static void launch_batch_tb(const gscl_batch* b, int kp, dim3 grid, dim3 blk, hipStream_t s, int parity,
+                            double omega) {
+    static_assert(gk::TB_KMAX == 4, "one instantiation per level count");
+    if (kp == 2) {
+        hipLaunchKernelGGL((batch_tb<MODE, RED, 2>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                           b->d_partials, parity, omega);
+    } else if (kp == 4) {
+        hipLaunchKernelGGL((batch_tb<MODE, RED, 4>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                           b->d_partials, parity, omega);
+    } else if constexpr (MODE != MODE_RBGS_TB) {
+        hipLaunchKernelGGL((batch_tb<MODE, RED, 3>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,
+                           b->d_partials, parity, omega);
+    }
+}
+
 static int enqueue_step(gscl_batch* b) {
     gscl_ctx* c = b->ctx;
     hipStream_t s = c->stream;
@@ -665,13 +694,13 @@ static int enqueue_step(gscl_batch* b) {
     const dim3 grid(b->persist_blocks), blk(64 * BNW);
     const int ms = b->desc.max_slots;
     const int kp = b->desc.sweeps_per_pass;
-    // blocked passes: one 16-wave block per CU in FP64, two in FP32
-    const dim3 tgrid(b->desc.precision == GSCL_PREC_F64 ? 256 : 512), tblk(64 * gk::TB_NW);
+    // blocked passes: two 16-wave blocks per CU in FP32 and in FP64
+    // two-level passes, else one (the LDS rows of the levels)
+    const dim3 tgrid(b->desc.precision == GSCL_PREC_F64 && kp > 2 ? 256 : 512), tblk(64 * gk::TB_NW);
     if (b->desc.method == GSCL_BATCH_RBGS) {
         if (kp > 1) {
             for (int q = 0; q < 2 * S / kp; ++q)  // even count: the step ends in u
-                hipLaunchKernelGGL((batch_tb<MODE_RBGS_TB, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state,
-                                   b->d_hdr, b->d_partials, q & 1, 0.0, kp);
+                launch_batch_tb<MODE_RBGS_TB, false>(b, kp, tgrid, tblk, s, q & 1, 0.0);
         } else {
             for (int k = 0; k < 2 * S; ++k)
                 hipLaunchKernelGGL((batch_sweep<MODE_RBGS, false>), grid, blk, 0, s, b->d_slots, b->d_state,
@@ -685,11 +714,9 @@ static int enqueue_step(gscl_batch* b) {
         const int np = S / kp;  // even: the step ends in u
         for (int q = 0; q < np; ++q) {
             if (q + 1 < np)
-                hipLaunchKernelGGL((batch_tb<MODE_F64, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
-                                   b->d_partials, q & 1, b->desc.omega, kp);
+                launch_batch_tb<MODE_F64, false>(b, kp, tgrid, tblk, s, q & 1, b->desc.omega);
             else
-                hipLaunchKernelGGL((batch_tb<MODE_F64, true>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
-                                   b->d_partials, q & 1, b->desc.omega, kp);
+                launch_batch_tb<MODE_F64, true>(b, kp, tgrid, tblk, s, q & 1, b->desc.omega);
         }
         hipLaunchKernelGGL(batch_finish, dim3(ms), dim3(256), 0, s, b->d_slots, b->d_state, b->d_hdr, b->d_partials,
                            rtol2, S, (long long)b->desc.max_sweeps, 0, 1);
@@ -712,8 +739,7 @@ static int enqueue_step(gscl_batch* b) {
                            rtol2, S, (long long)b->desc.max_sweeps, 1, 0);
         if (kp > 1) {
             for (int q = 0; q < S / kp; ++q)
-                hipLaunchKernelGGL((batch_tb<MODE_F32, false>), tgrid, tblk, 0, s, b->d_slots, b->d_state, b->d_hdr,
-                                   b->d_partials, q & 1, b->desc.omega, kp);
+                launch_batch_tb<MODE_F32, false>(b, kp, tgrid, tblk, s, q & 1, b->desc.omega);
         } else {
             for (int k = 1; k <= S; ++k)
                 hipLaunchKernelGGL((batch_sweep<MODE_F32, false>), grid, blk, 0, s, b->d_slots, b->d_state, b->d_hdr,

@@ -44,13 +44,36 @@ struct TBArgs {
     const void* f;    // right-hand side (may be null)
     void* out;        // level k
     double p[8];      // operator parameters of the plain sweep (RB: p[3] = first colour)
-    int k;            // sweeps (colour passes) per pass, 1..KMAX
+    int k;            // sweeps (colour passes) per pass, 1..TB_KMAX (the
+                      // kernels take it as the template parameter K)
     int ntx, nty, ncz, cz;
     int operand;
     RedArgs ra;
 };
 
 constexpr int TB_NW = 16, TB_RPW = 2, TB_ROWS = TB_NW * TB_RPW;
+
+// Waves per SIMD that a K-level kernel is compiled for: two 16-wave blocks
+// per CU where two blocks' LDS rows (4096 K sizeof(T) bytes each) fit in the
+// 160 KB, else one; the register budget follows (64 or 128 VGPRs).  The
+// variants with a fused reduction at K = 2 in FP64, and with a fused
+// reduction and red-black levels at K = 4 in FP32, do not fit 64 VGPRs and
+// take one block.
+template <class T, int K, bool RED, bool RB>
+constexpr int tb_waves_per_eu() {
+    if (RED && (sizeof(T) == 8 ? K == 2 : K == 4 && RB)) return 4;
+    return 2 * 4096 * K * (int)sizeof(T) + 1024 <= 160 * 1024 ? 8 : 4;
+}
+
+// Steps per written-out group of the z march: 2 (the period of the level
+// windows, so their shifts become register renamings rather than moves) for
+// the variants where that measured faster and fits the register budget
+// without spilling (FP64 at K = 3, plain FP32 Jacobi at K = 4), else 1.
+template <class T, int K, bool RED, bool RB>
+constexpr int tb_unroll() {
+    if (sizeof(T) == 8) return K == 3 ? 2 : 1;
+    return K == 4 && !RED && !RB ? 2 : 1;
+}
 
 // Value of the lane below (lane - 1) or above (lane + 1) in the wave, by
 // wave-wide DPP shifts (wave_shr:1 / wave_shl:1); lanes without a source get 0.
@@ -67,20 +90,23 @@ __device__ __forceinline__ double lane_shift(double v) {
 }
 constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
 
-// One output tile (index `tile` of a.ntx x a.nty x a.ncz): k levels over its
-// z chunk; with RED, the fused operand of level k is added to acc.  Every
-// thread of the 16-wave block calls it.
-template <class T, bool HAS_F, int KMAX, bool RED, bool RB>
+// One output tile (index `tile` of a.ntx x a.nty x a.ncz): K levels over its
+// z chunk; with RED, the fused operand of level K is added to acc.  Every
+// thread of the 16-wave block calls it.  K is a template parameter, so the
+// level loop unrolls to straight-line code with no per-level branches.
+template <class T, bool HAS_F, int K, bool RED, bool RB, int UNROLL = tb_unroll<T, K, RED, RB>()>
 __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double& acc) {
+    static_assert(UNROLL == 1 || UNROLL == 2, "steps per group");
     using Op = typename std::conditional<RB, OpRBGS<T, HAS_F>, OpWJacobi<T, T, 3, HAS_F>>::type;
     constexpr int R = TB_RPW;
     // the rows every wave stages per level, in two copies alternating by
     // step: a step's staging writes the copy the previous step did not read,
-    // so one barrier per step suffices (FP64: 128 KB, one block per CU)
-    __shared__ T lds[2][KMAX][TB_NW][R][64];
+    // so one barrier per step suffices (FP64 at K = 4: 128 KB, one block
+    // per CU)
+    __shared__ T lds[2][K][TB_NW][R][64];
 
     const Geo& g = a.g;
-    const int k = a.k;
+    constexpr int k = K;
     const int ox = 64 - 2 * k, oy = TB_ROWS - 2 * k;  // output tile
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // waves whose rows border this wave's (the block's edge waves read their
@@ -95,90 +121,120 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
     const bool x_out = lane >= k && lane < 64 - k && x_in;
     const T bcv = (T)g.bcv;
 
-    int row[R], ys[R], yg[R];
-    bool y_in[R], y_out[R];
+    int row[R], yg[R];
+    bool xy_in[R], y_out[R];
+    // byte offset of this thread's column within a plane: 32 bits (the
+    // launchers refuse planes of 4 GiB or more), so each access is a
+    // wave-uniform 64-bit plane address plus one 32-bit register
+    uint32_t roff[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         row[i] = w * R + i;
         const int y = yt * oy - k + row[i];
         yg[i] = y;
-        y_in[i] = (unsigned)y < (unsigned)g.ny;
-        ys[i] = y_in[i] ? y : wrap_idx(y, g.ny, dir ? BC_CLAMP : g.bc);
-        y_out[i] = row[i] >= k && row[i] < TB_ROWS - k && y_in[i];
+        const bool y_in = (unsigned)y < (unsigned)g.ny;
+        const int ys = y_in ? y : wrap_idx(y, g.ny, dir ? BC_CLAMP : g.bc);
+        roff[i] = (uint32_t)(((int64_t)ys * g.py + xs) * (int64_t)sizeof(T));
+        xy_in[i] = y_in && x_in;
+        y_out[i] = row[i] >= k && row[i] < TB_ROWS - k && y_in;
     }
+    const T* const ub = static_cast<const T*>(a.u);
+    const T* const fb = static_cast<const T*>(a.f);
+    T* const ob = static_cast<T*>(a.out);
 
-    // level-0 value of this thread's column at plane z
-    auto load_u = [&](int z, int i) __attribute__((always_inline)) -> T {
-        const bool z_in = (unsigned)z < (unsigned)g.nz;
-        const int zz = z_in ? z : wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc);
-        const T v = static_cast<const T*>(a.u)[(int64_t)zz * g.pz + (int64_t)ys[i] * g.py + xs];
-        return (dir && !(z_in && y_in[i] && x_in)) ? bcv : v;
+    // element offset of the plane read for z: lin (= z * pz) inside the
+    // grid, the wrapped (periodic) or clamped (Dirichlet) plane outside.
+    // Plane offsets are wave-uniform and computed once per step for both
+    // rows; the right-hand side of plane s reuses the offset of the input
+    // plane s loaded one step earlier.
+    auto plane_off = [&](int z, int64_t lin) __attribute__((always_inline)) -> int64_t {
+        if ((unsigned)z < (unsigned)g.nz) return lin;
+        return (int64_t)wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc) * g.pz;
     };
-    auto load_f = [&](int z, int i) __attribute__((always_inline)) -> T {
+    // level-0 value of row i at plane z (plane offset off)
+    auto load_u = [&](int z, int64_t off, int i) __attribute__((always_inline)) -> T {
+        const T v = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(ub + off) + roff[i]);
+        return (dir && !((unsigned)z < (unsigned)g.nz && xy_in[i])) ? bcv : v;
+    };
+    auto load_f = [&](int64_t off, int i) __attribute__((always_inline)) -> T {
         if (!HAS_F) return T(0);
-        const int zz = (unsigned)z < (unsigned)g.nz ? z : wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc);
-        return static_cast<const T*>(a.f)[(int64_t)zz * g.pz + (int64_t)ys[i] * g.py + xs];
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(fb + off) + roff[i]);
     };
 
     // at the start of step s: hist[L][i][1] = level L at plane s-1-L (the
     // previous step's value), hist[L][i][0] = level L at plane s-2-L;
     // fq[t][i] = f at plane s-t once the step has shifted the queue
-    T hist[KMAX][R][2];
-    T fq[KMAX + 1][R];
+    T hist[K][R][2];
+    T fq[K + 1][R];
 #pragma unroll
-    for (int L = 0; L < KMAX; ++L)
+    for (int L = 0; L < K; ++L)
 #pragma unroll
         for (int i = 0; i < R; ++i) hist[L][i][0] = hist[L][i][1] = T(0);
 #pragma unroll
-    for (int t = 0; t <= KMAX; ++t)
+    for (int t = 0; t <= K; ++t)
 #pragma unroll
         for (int i = 0; i < R; ++i) fq[t][i] = T(0);
 
     // the first step whose level-k output is needed is s = z0 + k; steps
     // from z0 - k on fill the windows (values below that are never used).
     // The next step's input rows are requested before the current step is
-    // computed.  (A two-step lookahead measured no faster in FP64 and cost
-    // FP32 half its resident blocks.)
+    // computed.  (A two-step lookahead measured no faster, FP32 and FP64.)
     const int s_begin = z0 - k, s_end = z1 + k;
+    // offset of plane s (set when its input row was loaded), the linear
+    // offset of plane s + 1, and that of the plane level K writes, s - K
+    int64_t off_cur = plane_off(s_begin, (int64_t)s_begin * g.pz);
+    int64_t lin_next = (int64_t)(s_begin + 1) * g.pz;
+    int64_t lin_st = (int64_t)(s_begin - k) * g.pz;
     T nu[R], nf[R];
+    {
+        const int64_t off_f = plane_off(s_begin - 1, (int64_t)(s_begin - 1) * g.pz);
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        nu[i] = load_u(s_begin, i);
-        nf[i] = load_f(s_begin - 1, i);
+        for (int i = 0; i < R; ++i) {
+            nu[i] = load_u(s_begin, off_cur, i);
+            nf[i] = load_f(off_f, i);
+        }
     }
 
-    for (int s = s_begin; s < s_end; ++s) {
+    // The march runs in whole groups of UNROLL steps (1 or 2), written out
+    // by hand: the compiler does not unroll a loop with a barrier and a
+    // variable trip count by itself.  A step past s_end (at most one) only
+    // computes: its planes lie beyond z1 + k, so nothing is stored or
+    // reduced, and its loads are of wrapped or clamped planes inside the
+    // grid.  The LDS copy of a step alternates with the step's parity.
+    for (int s0 = s_begin; s0 < s_end; s0 += UNROLL)
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        const int s = s0 + u;
         T cur[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             cur[i] = nu[i];
 #pragma unroll
-            for (int t = KMAX; t >= 2; --t) fq[t][i] = fq[t - 1][i];
+            for (int t = K; t >= 2; --t) fq[t][i] = fq[t - 1][i];
             fq[1][i] = nf[i];
         }
-        if (s + 1 < s_end) {
+        {
+            const int64_t off_next = plane_off(s + 1, lin_next);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                nu[i] = load_u(s + 1, i);
-                nf[i] = load_f(s, i);
+                nu[i] = load_u(s + 1, off_next, i);
+                nf[i] = load_f(off_cur, i);
             }
+            off_cur = off_next;
         }
         // stage level t-1 of plane s-t for every level t
-        T(*lb)[TB_NW][R][64] = lds[(s - s_begin) & 1];
+        T(*lb)[TB_NW][R][64] = lds[UNROLL == 2 ? u : (s - s_begin) & 1];
 #pragma unroll
-        for (int t = 1; t <= KMAX; ++t) {
-            if (t > k) break;
+        for (int t = 1; t <= K; ++t)
 #pragma unroll
             for (int i = 0; i < R; ++i) lb[t - 1][w][i][lane] = hist[t - 1][i][1];
-        }
         __syncthreads();
         // newest value of the level below, per row
         T below[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) below[i] = cur[i];
 #pragma unroll
-        for (int t = 1; t <= KMAX; ++t) {
-            if (t > k) break;
+        for (int t = 1; t <= K; ++t) {
             const int zp = s - t;
             const bool z_in = (unsigned)zp < (unsigned)g.nz;
             // red-black: this level's colour in p[3]
@@ -205,11 +261,11 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
                 T o[1];
                 double rv[1];
                 Op::apply(st, av, bv, pt, o, rv, a.operand);
-                const bool inside = z_in && y_in[i] && x_in;
+                const bool inside = z_in && xy_in[i];
                 const T val = (dir && !inside) ? bcv : o[0];
                 if (t == k) {
                     if (x_out && y_out[i] && zp >= z0 && zp < z1) {
-                        static_cast<T*>(a.out)[(int64_t)zp * g.pz + (int64_t)ys[i] * g.py + xs] = val;
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(ob + lin_st) + roff[i]) = val;
                         if (RED) acc = red_acc(acc, rv[0], a.ra.op);
                     }
                 }
@@ -220,14 +276,16 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
                 below[i] = val;
             }
         }
+        lin_next += g.pz;
+        lin_st += g.pz;
     }
 }
 
-template <class T, bool HAS_F, int KMAX, bool RED, bool RB>
-__global__ __launch_bounds__(64 * TB_NW) void tb7_sweep(TBArgs a) {
+template <class T, bool HAS_F, int K, bool RED, bool RB>
+__global__ __launch_bounds__(64 * TB_NW, (tb_waves_per_eu<T, K, RED, RB>())) void tb7_sweep(TBArgs a) {
     const int tile = xcd_remap(blockIdx.x, a.ntx * a.nty * a.ncz);
     double acc = 0.0;
-    tb7_tile<T, HAS_F, KMAX, RED, RB>(a, tile, acc);
+    tb7_tile<T, HAS_F, K, RED, RB>(a, tile, acc);
     if (RED) block_reduce(acc, a.ra, tile);
 }
 

@@ -90,23 +90,42 @@ def test_tb_errors(ctx):
     assert err(lambda: ctx.do_all(G.K_WJACOBI_TB, [g2], [h2], p=(1.0, 1.0, 2))) == G.ERR_SHAPE
 
 
-def test_tb_full_size_512_f64_bitwise(ctx):
-    """512^3 FP64 with a right-hand side, default tile, k = 4 against 4 sweeps."""
+@pytest.mark.parametrize("dt,k", [(G.F64, 4), (G.F64, 3), (G.F32, 4), (G.F32, 2)])
+def test_tb_full_size_512_bitwise(ctx, dt, k):
+    """512^3 with a right-hand side, default tile, k levels against k sweeps
+    (FP64 k = 3 and FP32 k = 4 march in two-step groups)."""
     import torch
     n = 512
     shape = (n, n, n)
-    gu = ctx.grid(shape, G.F64, halo=1)
-    gf = ctx.grid(shape, G.F64, halo=0)
+    tt = torch.float64 if dt == G.F64 else torch.float32
+    gu = ctx.grid(shape, dt, halo=1)
+    gf = ctx.grid(shape, dt, halo=0)
     gen = torch.Generator(device="cuda").manual_seed(5)
-    gu.view.copy_(torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen))
-    gf.view.copy_(torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen))
-    a = ctx.grid(shape, G.F64, halo=1)
-    b = ctx.grid(shape, G.F64, halo=1)
+    gu.view.copy_(torch.randn(shape, dtype=tt, device="cuda", generator=gen))
+    gf.view.copy_(torch.randn(shape, dtype=tt, device="cuda", generator=gen))
+    a = ctx.grid(shape, dt, halo=1)
+    b = ctx.grid(shape, dt, halo=1)
     a.view.copy_(gu.view)
     h2 = 1.0 / (n + 1) ** 2
-    for _ in range(4):
+    for _ in range(k):
         ctx.do_all(G.K_WJACOBI, [a, gf], [b], p=(6 / 7, h2))
         a, b = b, a
-    go = ctx.grid(shape, G.F64, halo=1)
-    ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [go], p=(6 / 7, h2, 4))
+    go = ctx.grid(shape, dt, halo=1)
+    ctx.do_all(G.K_WJACOBI_TB, [gu, gf], [go], p=(6 / 7, h2, k))
     assert torch.equal(go.view, a.view)
+
+
+def test_tb_refuses_planes_of_4_gib(ctx):
+    """The blocked kernels address a point within its plane by a 32-bit byte
+    offset: an FP64 plane of 23200 x 23200 points (4.3 GB) is refused before
+    any launch.  (The grids, one plane each, are allocated, never written.)"""
+    import torch
+    shape = (1, 23200, 23200)
+    gu = ctx.grid(shape, G.F64, halo=1)
+    go = ctx.grid(shape, G.F64, halo=1)
+    for kind, p in ((G.K_WJACOBI_TB, (1.0, 1.0, 2)), (G.K_RBGS_TB, (1.0, 1.0, 0, 2))):
+        with pytest.raises(G.GsclError) as e:
+            ctx.do_all(kind, [gu], [go], p=p)
+        assert e.value.code == G.ERR_SHAPE
+    del gu, go
+    torch.cuda.empty_cache()
