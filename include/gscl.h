@@ -370,7 +370,7 @@ typedef struct {
     int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f),
                                    GSCL_K_RBGS (Poisson by red-black Gauss-Seidel /
                                    SOR, F64: colour passes in place, or on grids of
-                                   144^3 points or more GSCL_K_RBGS_TB passes of up
+                                   72^3 points or more GSCL_K_RBGS_TB passes of up
                                    to 4 colour passes through a workspace grid; the
                                    check follows each chunk as a separate residual
                                    pass), or

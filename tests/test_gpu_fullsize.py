@@ -129,9 +129,9 @@ def test_batch_mixed_sizes_up_to_192(sctx):
         assert math.sqrt(oracle.sumsq(res) / oracle.sumsq(f)) <= 1e-8
 
 
-@pytest.mark.parametrize("n,S", [(150, 10), (150, 6), (160, 4)])
+@pytest.mark.parametrize("n,S", [(150, 10), (150, 6), (160, 4), (90, 10)])
 def test_poisson_temporal_chunks_match_closed_form_trace(sctx, n, S):
-    """Grids of 144^3 points or more run their chunks as temporally blocked
+    """Grids of 72^3 points or more run their chunks as temporally blocked
     passes (S = 10 -> 4+4+1+1, 6 -> 4+2, 4 -> 2+2): same stopping sweep as
     the closed-form residual trace, and the oracle's residual of the answer."""
     ctx = sctx

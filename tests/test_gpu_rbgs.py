@@ -197,9 +197,9 @@ def test_rbgs_blocked_errors(ctx):
     assert err(lambda: ctx.do_all(G.K_RBGS_TB, [g8], [h8], p=(1.0, 1.0, 0, 2))) == G.ERR_DTYPE
 
 
-@pytest.mark.parametrize("n,S", [(150, 6), (146, 4)])
+@pytest.mark.parametrize("n,S", [(150, 6), (146, 4), (75, 6)])
 def test_blocked_sor_solve_equals_inplace_solve(sctx, n, S):
-    """Grids of 144^3 points or more run the SOR chunks as blocked passes
+    """Grids of 72^3 points or more run the SOR chunks as blocked passes
     (2S colour passes: S = 6 -> 4+4+2+2, S = 4 -> 4+4): the same stopping
     sweep and the same iterate, bit for bit, as in-place colour passes with
     the same residual checks, and the oracle accepts the answer."""
