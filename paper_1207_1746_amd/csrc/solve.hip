@@ -28,9 +28,8 @@ struct TmpGrid {
 size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Poisson chunks on grids of at least 72^3 points run temporally blocked
-// passes (whole solves measured 1.3-1.8 x faster at 80^3-112^3 and equal at
-// 144^3-160^3; 5% slower at 64^3, and at 128^3, where the plain tiles fit
-// the grid exactly).
+// passes (whole solves measured 1.3-1.8 x faster at 80^3-112^3; 4-10%
+// slower at 64^3, and at 128^3, where the plain tiles fit the grid exactly).
 bool blocked_passes(const gscl_grid_desc& d) { return d.n[0] * d.n[1] * d.n[2] >= (int64_t)72 * 72 * 72; }
 
 // Split n sweeps (or colour passes) into passes of at most TB_KMAX, with an
