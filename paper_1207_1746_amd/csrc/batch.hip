@@ -204,11 +204,10 @@ void batch_tb(const BSlot* __restrict__ slots, const BState* st, const BHeader* 
             a.f = s.f;
         }
         double acc = 0.0;
-        // (the FP32 four-level pass keeps one step per group: with the slot
-        // bookkeeping, two would spill)
+        // slots of blocked batches span fewer than 2^32 elements (admission),
+        // so the march keeps 32-bit plane offsets
         constexpr bool RB = MODE == MODE_RBGS_TB;
-        constexpr int U = MODE == MODE_F32 && K == 4 ? 1 : gk::tb_unroll<T, K, RED, RB>();
-        gk::tb7_tile<T, true, K, RED, RB, U>(a, t - s.tb_begin, acc);
+        gk::tb7_tile<T, true, K, RED, RB, true>(a, t - s.tb_begin, acc);
         if (RED) gk::block_reduce(acc, a.ra, t);
     }
 }
@@ -579,10 +578,12 @@ extern "C" int gscl_batch_admit(gscl_batch* b, gscl_grid* u, const gscl_grid* f,
     if (u->d.halo < 1) return gscl_fail(GSCL_ERR_HALO, "u must declare halo >= 1");
     if (!(h2 > 0)) return gscl_fail(GSCL_ERR_ARG, "h2 must be positive");
     if (u->d.n[0] * u->d.n[1] * u->d.n[2] == 0) return gscl_fail(GSCL_ERR_SHAPE, "empty grid");
-    // blocked passes address a point as a plane address plus a 32-bit byte
-    // offset within the plane
-    if (b->desc.sweeps_per_pass > 1 && ((u->d.n[1] - 1) * u->d.pitch[0] + u->d.n[0]) * 8 > (int64_t)UINT32_MAX)
-        return gscl_fail(GSCL_ERR_SHAPE, "blocked passes need planes under 4 GiB");
+    // blocked passes address a point as a 32-bit plane offset (in elements,
+    // halo planes included) plus a 32-bit byte offset within the plane
+    if (b->desc.sweeps_per_pass > 1 &&
+        (((u->d.n[1] - 1) * u->d.pitch[0] + u->d.n[0]) * 8 > (int64_t)UINT32_MAX ||
+         u->d.pitch[1] * (u->d.n[2] + 2 * (int64_t)u->d.halo) > (int64_t)UINT32_MAX))
+        return gscl_fail(GSCL_ERR_SHAPE, "blocked passes need planes under 4 GiB and grids under 2^32 points");
     int id = -1;
     for (int i = 0; i < b->desc.max_slots; ++i)
         if (!b->used[i]) {

@@ -68,10 +68,12 @@ constexpr int tb_waves_per_eu() {
 // Steps per written-out group of the z march: 2 (the period of the level
 // windows, so their shifts become register renamings rather than moves) for
 // the variants where that measured faster and fits the register budget
-// without spilling (FP64 at K = 3, plain FP32 Jacobi at K = 4), else 1.
-template <class T, int K, bool RED, bool RB>
+// without spilling (FP64 at K = 3, and at K = 4 with 32-bit plane offsets
+// and not both a fused reduction and red-black levels; plain FP32 Jacobi
+// at K = 4), else 1.
+template <class T, int K, bool RED, bool RB, bool OFF32>
 constexpr int tb_unroll() {
-    if (sizeof(T) == 8) return K == 3 ? 2 : 1;
+    if (sizeof(T) == 8) return K == 3 || (K == 4 && OFF32 && !(RED && RB)) ? 2 : 1;
     return K == 4 && !RED && !RB ? 2 : 1;
 }
 
@@ -94,9 +96,13 @@ constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
 // z chunk; with RED, the fused operand of level K is added to acc.  Every
 // thread of the 16-wave block calls it.  K is a template parameter, so the
 // level loop unrolls to straight-line code with no per-level branches.
-template <class T, bool HAS_F, int K, bool RED, bool RB, int UNROLL = tb_unroll<T, K, RED, RB>()>
+// OFF32: every plane offset of the grid, (nz - 1) pz, fits 32 bits, so the
+// march keeps its plane offsets in fewer scalar registers.
+template <class T, bool HAS_F, int K, bool RED, bool RB, bool OFF32,
+          int UNROLL = tb_unroll<T, K, RED, RB, OFF32>()>
 __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double& acc) {
     static_assert(UNROLL == 1 || UNROLL == 2, "steps per group");
+    using Off = typename std::conditional<OFF32, uint32_t, int64_t>::type;
     using Op = typename std::conditional<RB, OpRBGS<T, HAS_F>, OpWJacobi<T, T, 3, HAS_F>>::type;
     constexpr int R = TB_RPW;
     // the rows every wave stages per level, in two copies alternating by
@@ -147,16 +153,16 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
     // Plane offsets are wave-uniform and computed once per step for both
     // rows; the right-hand side of plane s reuses the offset of the input
     // plane s loaded one step earlier.
-    auto plane_off = [&](int z, int64_t lin) __attribute__((always_inline)) -> int64_t {
+    auto plane_off = [&](int z, Off lin) __attribute__((always_inline)) -> Off {
         if ((unsigned)z < (unsigned)g.nz) return lin;
-        return (int64_t)wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc) * g.pz;
+        return (Off)((int64_t)wrap_idx(z, g.nz, dir ? BC_CLAMP : g.bc) * g.pz);
     };
     // level-0 value of row i at plane z (plane offset off)
-    auto load_u = [&](int z, int64_t off, int i) __attribute__((always_inline)) -> T {
+    auto load_u = [&](int z, Off off, int i) __attribute__((always_inline)) -> T {
         const T v = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(ub + off) + roff[i]);
         return (dir && !((unsigned)z < (unsigned)g.nz && xy_in[i])) ? bcv : v;
     };
-    auto load_f = [&](int64_t off, int i) __attribute__((always_inline)) -> T {
+    auto load_f = [&](Off off, int i) __attribute__((always_inline)) -> T {
         if (!HAS_F) return T(0);
         return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(fb + off) + roff[i]);
     };
@@ -182,12 +188,14 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
     const int s_begin = z0 - k, s_end = z1 + k;
     // offset of plane s (set when its input row was loaded), the linear
     // offset of plane s + 1, and that of the plane level K writes, s - K
-    int64_t off_cur = plane_off(s_begin, (int64_t)s_begin * g.pz);
-    int64_t lin_next = (int64_t)(s_begin + 1) * g.pz;
-    int64_t lin_st = (int64_t)(s_begin - k) * g.pz;
+    // (32-bit offsets wrap below plane 0; they are used only once they
+    // have been advanced into the grid, where modular sums are exact)
+    Off off_cur = plane_off(s_begin, (Off)((int64_t)s_begin * g.pz));
+    Off lin_next = (Off)((int64_t)(s_begin + 1) * g.pz);
+    Off lin_st = (Off)((int64_t)(s_begin - k) * g.pz);
     T nu[R], nf[R];
     {
-        const int64_t off_f = plane_off(s_begin - 1, (int64_t)(s_begin - 1) * g.pz);
+        const Off off_f = plane_off(s_begin - 1, (Off)((int64_t)(s_begin - 1) * g.pz));
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             nu[i] = load_u(s_begin, off_cur, i);
@@ -214,7 +222,7 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
             fq[1][i] = nf[i];
         }
         {
-            const int64_t off_next = plane_off(s + 1, lin_next);
+            const Off off_next = plane_off(s + 1, lin_next);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 nu[i] = load_u(s + 1, off_next, i);
@@ -276,16 +284,16 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
                 below[i] = val;
             }
         }
-        lin_next += g.pz;
-        lin_st += g.pz;
+        lin_next += (Off)g.pz;
+        lin_st += (Off)g.pz;
     }
 }
 
-template <class T, bool HAS_F, int K, bool RED, bool RB>
+template <class T, bool HAS_F, int K, bool RED, bool RB, bool OFF32>
 __global__ __launch_bounds__(64 * TB_NW, (tb_waves_per_eu<T, K, RED, RB>())) void tb7_sweep(TBArgs a) {
     const int tile = xcd_remap(blockIdx.x, a.ntx * a.nty * a.ncz);
     double acc = 0.0;
-    tb7_tile<T, HAS_F, K, RED, RB>(a, tile, acc);
+    tb7_tile<T, HAS_F, K, RED, RB, OFF32>(a, tile, acc);
     if (RED) block_reduce(acc, a.ra, tile);
 }
 
