@@ -129,3 +129,31 @@ def test_tb_refuses_planes_of_4_gib(ctx):
         assert e.value.code == G.ERR_SHAPE
     del gu, go
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("bc", [G.DIRICHLET, G.PERIODIC])
+def test_tb_64bit_plane_offsets_bitwise(ctx, bc):
+    """Plane offsets that do not fit 32 bits take the kernel with 64-bit
+    offsets: an FP32 grid of 9 planes 2^29 elements apart (the last plane at
+    element 2^32) against k plain sweeps, bit for bit; under the periodic rule
+    the wrapped plane below the first is that last plane.  (Four 18 GB
+    allocations; only each plane's first rows are written.)"""
+    import torch
+    shape = (9, 8, 64)
+    pitch = (64, 1 << 29)
+    g = np.random.default_rng(29)
+    u = g.standard_normal(shape)
+    omega, h2 = 0.8, 0.25
+    bcv = 0.5 if bc == G.DIRICHLET else 0.0
+    grids = [ctx.grid(shape, G.F32, halo=1, bc=bc, bc_value=bcv, pitch=pitch) for _ in range(4)]
+    gu, go, a, b = grids
+    gu.upload(u)
+    for k in (3, 4):
+        a.upload(u)
+        for _ in range(k):
+            ctx.do_all(G.K_WJACOBI, [a], [b], p=(omega, h2))
+            a, b = b, a
+        ctx.do_all(G.K_WJACOBI_TB, [gu], [go], p=(omega, h2, k))
+        assert torch.equal(go.view, a.view), k
+    del grids, gu, go, a, b
+    torch.cuda.empty_cache()
