@@ -92,6 +92,13 @@ __device__ __forceinline__ double lane_shift(double v) {
 }
 constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
 
+// a * b rounded once, never fused with a later sum
+template <class T>
+__device__ __forceinline__ T exact_mul(T a, T b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 // One output tile (index `tile` of a.ntx x a.nty x a.ncz): K levels over its
 // z chunk; with RED, the fused operand of level K is added to acc.  Every
 // thread of the 16-wave block calls it.  K is a template parameter, so the
@@ -162,9 +169,16 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
         const T v = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(ub + off) + roff[i]);
         return (dir && !((unsigned)z < (unsigned)g.nz && xy_in[i])) ? bcv : v;
     };
+    // Without a fused reduction the right-hand side is held as h^2 f, formed
+    // once per loaded value instead of once per level, and the operator is
+    // given h^2 = 1: the product it forms is then exact, so every level
+    // rounds as the plain sweep does.  (A fused residual needs f itself.)
+    constexpr bool PRE_H2 = HAS_F && !RED;
+    const T h2 = (T)a.p[1];
     auto load_f = [&](Off off, int i) __attribute__((always_inline)) -> T {
         if (!HAS_F) return T(0);
-        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(fb + off) + roff[i]);
+        const T f = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(fb + off) + roff[i]);
+        return PRE_H2 ? exact_mul(h2, f) : f;
     };
 
     // at the start of step s: hist[L][i][1] = level L at plane s-1-L (the
@@ -246,8 +260,8 @@ __device__ __forceinline__ void tb7_tile(const TBArgs& a, const int tile, double
             const int zp = s - t;
             const bool z_in = (unsigned)zp < (unsigned)g.nz;
             // red-black: this level's colour in p[3]
-            const double pl[4] = {a.p[0], a.p[1], a.p[2], (double)(((int)a.p[3] + t - 1) & 1)};
-            const double* pt = RB ? pl : a.p;
+            const double pl[4] = {a.p[0], PRE_H2 ? 1.0 : a.p[1], a.p[2], (double)(((int)a.p[3] + t - 1) & 1)};
+            const double* pt = pl;
             // level t-1 of plane s-t, this wave's rows
             T cc[R];
 #pragma unroll
