@@ -29,8 +29,13 @@ size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Poisson chunks on grids of at least 72^3 points run temporally blocked
 // passes (whole solves measured 1.3-1.8 x faster at 80^3-112^3; 4-10%
-// slower at 64^3, and at 128^3, where the plain tiles fit the grid exactly).
-bool blocked_passes(const gscl_grid_desc& d) { return d.n[0] * d.n[1] * d.n[2] >= (int64_t)72 * 72 * 72; }
+// slower at 64^3, and at 128^3, where the plain tiles fit the grid exactly),
+// unless a plane spans 4 GiB or more (the blocked kernels' in-plane offsets
+// are 32-bit; the plain sweeps serve such grids).
+bool blocked_passes(const gscl_grid_desc& d) {
+    const bool plane_fits = ((d.n[1] - 1) * d.pitch[0] + d.n[0]) * (int64_t)sizeof(double) <= (int64_t)UINT32_MAX;
+    return plane_fits && d.n[0] * d.n[1] * d.n[2] >= (int64_t)72 * 72 * 72;
+}
 
 // Split n sweeps (or colour passes) into passes of at most TB_KMAX, with an
 // even pass count so that a ping-pong chunk ends in the caller's grid.
