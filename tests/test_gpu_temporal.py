@@ -157,3 +157,31 @@ def test_tb_64bit_plane_offsets_bitwise(ctx, bc):
         assert torch.equal(go.view, a.view), k
     del grids, gu, go, a, b
     torch.cuda.empty_cache()
+
+
+def test_solve_keeps_plain_sweeps_for_planes_of_4_gib(ctx):
+    """A Poisson solve on a grid whose planes span 4 GiB (3 rows of 124416
+    points, 2^28 + 64 elements apart) runs plain sweeps instead of blocked
+    passes: it stops on the sweep limit (not on a shape error) with the
+    iterate of 4 plain sweeps, bit for bit.  (About 40 GB allocated.)"""
+    import torch
+    shape = (1, 3, 124416)
+    py = (1 << 28) + 64
+    pitch = (py, 3 * py)
+    g = np.random.default_rng(31)
+    f = g.standard_normal(shape)
+    h2 = 1e-4
+    gf = ctx.grid(shape, G.F64, halo=0, pitch=pitch)
+    gf.upload(f)
+    gu = ctx.grid(shape, G.F64, halo=1, pitch=pitch).fill(0.0)
+    with pytest.raises(G.GsclError) as e:
+        ctx.solve(G.K_WJACOBI, [gu], [gf], omega=6 / 7, h2=h2, rtol=1e-30, check_every=2, max_sweeps=4)
+    assert e.value.code == G.ERR_NOCONV
+    a = ctx.grid(shape, G.F64, halo=1, pitch=pitch).fill(0.0)
+    b = ctx.grid(shape, G.F64, halo=1, pitch=pitch)
+    for _ in range(4):
+        ctx.do_all(G.K_WJACOBI, [a, gf], [b], p=(6 / 7, h2))
+        a, b = b, a
+    assert torch.equal(gu.view, a.view)
+    del gf, gu, a, b
+    torch.cuda.empty_cache()
