@@ -244,11 +244,12 @@ gk::TileCfg pick_tile(gscl_ctx* c, int kind, int dtype, const gscl_grid_desc& d)
     const int64_t nx = d.n[0];
     if (kind == GSCL_K_WJACOBI_TB || kind == GSCL_K_RBGS_TB) {
         // output planes per block (measured on MI355X from 64^3 to 512^3): the
-        // largest power of two up to (output tiles per plane) * nz / 160,
-        // within 1..64 -- long enough to amortize the 2k warm-up planes, short
-        // enough for about one block per CU on mid-size grids
+        // largest power of two up to (output tiles per plane) * nz / 160 in
+        // FP64 and / 320 in FP32, within 1..64 -- long enough to amortize the
+        // 2k warm-up planes, short enough for about one resident block per
+        // block slot on mid-size grids (FP32 fits two blocks per CU)
         const int64_t cols = ((nx + 55) / 56) * ((d.n[1] + 23) / 24);
-        const int64_t want = std::max<int64_t>(1, cols * d.n[2] / 160);
+        const int64_t want = std::max<int64_t>(1, cols * d.n[2] / (dtype == GSCL_F32 ? 320 : 160));
         int64_t cz = 1;
         while (cz * 2 <= want && cz < 64) cz *= 2;
         t.V = 1;
