@@ -152,7 +152,9 @@ typedef struct gscl_batch gscl_batch;
  *   Dirichlet or periodic rule (CLAMP: GSCL_ERR_UNSUPPORTED).  The result is
  *   bitwise the one k separate WJACOBI sweeps give; fused operands refer to
  *   the last sweep (UPDATE = u_k - u_{k-1}, RESIDUAL of u_{k-1}).  Its tile
- *   uses only cz (output planes per block).
+ *   uses only cz (output planes per block).  A point is addressed within its
+ *   plane by a 32-bit byte offset: grids whose planes span 4 GiB or more
+ *   ((n[1]-1) * pitch[0] + n[0] elements) return GSCL_ERR_SHAPE.
  * GSCL_K_RBGS (Section 3 stateful stencils: red-black Gauss-Seidel / SOR):
  *   one colour pass in place.  in = {u} or {u, f}; out = {u} (the same grid
  *   as in[0]; f may not overlap it); p[0] = omega, p[1] = h^2, p[2] = colour.
@@ -168,7 +170,7 @@ typedef struct gscl_batch gscl_batch;
  *   p[1] = h^2, p[2] = first colour, p[3] = k in 1..4 (k = 2m: m full
  *   red-black sweeps).  ndim 3, F64 or F32, Dirichlet rule.  The result is
  *   bitwise the one k in-place passes give; fused operands refer to the last
- *   pass.  Tiles as GSCL_K_WJACOBI_TB.
+ *   pass.  Tiles and the plane limit as GSCL_K_WJACOBI_TB.
  *
  * Operators of the ordered line iteration spaces (gscl_do_line below).  The
  * value the operator wrote at the previously processed cell of a line is
@@ -370,7 +372,8 @@ typedef struct {
     int32_t kind;               /* GSCL_K_WJACOBI (Poisson, Lap_h u = f),
                                    GSCL_K_RBGS (Poisson by red-black Gauss-Seidel /
                                    SOR, F64: colour passes in place, or on grids of
-                                   72^3 points or more GSCL_K_RBGS_TB passes of up
+                                   72^3 points or more with planes under 4 GiB
+                                   GSCL_K_RBGS_TB passes of up
                                    to 4 colour passes through a workspace grid; the
                                    check follows each chunk as a separate residual
                                    pass), or
@@ -425,7 +428,10 @@ typedef struct {
                                    tiles, the same results bit for bit): Jacobi: k sweeps,
                                    sweeps_per_step a multiple of 2k; red-black: k colour
                                    passes, k even, sweeps_per_step a multiple of k (one more
-                                   F64 grid per slot) */
+                                   F64 grid per slot); blocked batches admit only grids
+                                   whose planes span under 4 GiB and whose points
+                                   (halo planes included) number under 2^32
+                                   (GSCL_ERR_SHAPE otherwise) */
 } gscl_batch_desc;
 typedef struct {
     int32_t state;              /* 0 free, 1 running, 2 converged, 3 failed */
