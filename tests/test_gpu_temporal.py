@@ -185,3 +185,21 @@ def test_solve_keeps_plain_sweeps_for_planes_of_4_gib(ctx):
     assert torch.equal(gu.view, a.view)
     del gf, gu, a, b
     torch.cuda.empty_cache()
+
+
+def test_tb_default_chunk_rule(ctx):
+    """Default z chunk of the blocked kinds: the largest power of two up to
+    (output tiles per plane) * nz / 160 in FP64 and / 320 in FP32, within
+    1..64 (512^3: 10 x 22 tiles per plane at k = 4 geometry)."""
+    for n, dt, cz in ((512, G.F64, 64), (512, G.F32, 64), (256, G.F64, 64), (256, G.F32, 32),
+                      (192, G.F64, 32), (192, G.F32, 16), (144, G.F64, 16), (96, G.F64, 4)):
+        tiles = -(-n // 56) * -(-n // 24)
+        want = max(1, tiles * n // (320 if dt == G.F32 else 160))
+        expect = 1
+        while expect * 2 <= want and expect < 64:
+            expect *= 2
+        assert expect == cz, (n, dt)
+        g = ctx.grid((n, n, n), dt, halo=1)
+        assert ctx.tile_get(G.K_WJACOBI_TB, g) == (1, 16, cz), (n, dt)
+        assert ctx.tile_get(G.K_RBGS_TB, g) == (1, 16, cz), (n, dt)
+        del g
