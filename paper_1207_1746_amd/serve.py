@@ -68,6 +68,14 @@ class ServeReport:
 
 
 class SolveServer:
+    """Continuous batching of Poisson solve requests on one GPU.
+
+    sweeps_per_step is also the residual-check period: every request's
+    convergence is tested once per step.  Longer steps spend less time in the
+    per-step residual, update and convergence passes but stop a request up to
+    one step late; on the N in [32, 192] request mix 256 sweeps served 18%
+    more solves/s than 64, and 512 fewer than 256."""
+
     def __init__(self, ctx: G.Context, precision: int = G.PREC_F32_IR, sweeps_per_step: int = 64,
                  rtol: float = 1e-8, omega: float = 6 / 7, max_slots: int = 64,
                  hbm_budget: int = 16 << 30, use_graph: bool = True, max_sweeps: int = 10 ** 7,
